@@ -1,0 +1,223 @@
+/*
+ * clf.h -- C-ABI of the MI355X split-step shallow-water library.
+ *
+ * The library advances the nonlinear shallow-water equations (paper section
+ * Numerics, eq1/eqABC: W_t = A W_x + B W_y + C with W = (h, u, v)) by the
+ * dimensionally split VTCS-2 scheme: per time step a 1-D sweep along x on
+ * every row (eq2A) then a 1-D sweep along y on every column (eq2B), each
+ * sweep advancing the Riemann invariants p = u + 2 sqrt(gh), q = u - 2 sqrt(gh)
+ * and the tangential velocity (pq1-pq3) with the depth-balanced difference
+ * Q (eqQ) and the solver2 stencil (or solver1), recovering u = (p+q)/2 and
+ * h = (p-q)^2/16g (stateu, stateh), inside the moving-cliff wet/dry cycle
+ * (a)-(e) of section Inundation algorithm.  Bathymetry is preprocessed at
+ * init against the depth-jump instability (section Numerical stability:
+ * dstab, newdw, newdc).  Outputs follow the paper's Running Options:
+ * maxwave, virtual gauges, boundary series for enclosed grids.
+ *
+ * Conventions
+ *   - Grids are row-major [ny][nx], x (longitude) fastest; depth is positive
+ *     down, negative on land (Running Options, Bathymetry data).
+ *   - Units: metres, seconds, decimal degrees for lon/lat.
+ *   - "device" pointers are HIP device memory on the context's device;
+ *     "host" pointers are host memory, read or written during the call.
+ *   - The caller owns every buffer.  The library places all its device data
+ *     in the caller's workspace (size from clf_workspace_bytes) and
+ *     allocates no device memory itself.
+ *   - All device work is enqueued on the stream given at init (a
+ *     hipStream_t passed as void*).  clf_step returns asynchronously;
+ *     device-detected errors (non-finite state) surface at the next
+ *     clf_sync, clf_get_state, clf_read_* or clf_get_raw_state.
+ *   - Every call returns CLF_OK (0) or a negative error code;
+ *     clf_last_error gives a message.  No exception crosses the ABI.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef CLF_H
+#define CLF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define CLF_OK 0
+#define CLF_EINVAL (-1)      /* bad shape, argument or coordinate */
+#define CLF_ECFL (-2)        /* still-water Courant number above the limit */
+#define CLF_EHIP (-3)        /* a HIP runtime call failed */
+#define CLF_ENONFINITE (-4)  /* the state became non-finite on the device */
+#define CLF_ESTATE (-5)      /* call made in the wrong order */
+#define CLF_ENOSPACE (-6)    /* workspace or record capacity too small */
+#define CLF_ESSL (-7)        /* depth preprocessing did not converge */
+
+/* coordinate systems (parameter file item 1) */
+#define CLF_CARTESIAN 0
+#define CLF_SPHERICAL 1
+
+/* arithmetic of the state and of the sweeps */
+#define CLF_FP64 0
+#define CLF_FP32 1
+
+/* split order: x then y every step, or x-y / y-x on even / odd steps */
+#define CLF_ORDER_XY 0
+#define CLF_ORDER_ALTERNATE 1
+
+/* sides of a grid */
+#define CLF_WEST 0
+#define CLF_EAST 1
+#define CLF_SOUTH 2
+#define CLF_NORTH 3
+
+/* clf_query keys */
+#define CLF_Q_MAX_CFL 1        /* max still-water Courant number sqrt(g d) dt / dx */
+#define CLF_Q_SSL_PASSES 2     /* passes of the depth preprocessing (0 if off) */
+#define CLF_Q_STEP 3           /* time steps done since clf_set_initial */
+#define CLF_Q_MIN_F 4          /* min over wet interior nodes of f_j (eq:f), both axes */
+#define CLF_Q_WORKSPACE 5      /* workspace bytes in use */
+#define CLF_Q_GAUGE_RECORDS 6  /* gauge records held */
+#define CLF_Q_TILES 7          /* wavefront tiles per step kernel launch */
+#define CLF_Q_SEGMENT 8        /* rows per wavefront tile (autotuned) */
+
+typedef struct clf_ctx clf_ctx;
+
+/* Grid (Running Options: Bathymetry data; parameter file item 1).
+ * x[nx], y[ny] are host arrays, strictly increasing: metres (Cartesian) or
+ * decimal degrees (spherical lon/lat).  A 2-D grid needs nx, ny >= 3; a 1-D
+ * grid has nx == 1 or ny == 1 and at least 3 nodes along the other axis. */
+typedef struct clf_grid {
+  int32_t nx, ny;
+  int32_t coord;
+  const double* x;
+  const double* y;
+} clf_grid;
+
+/* Parameters (parameter file items 5-18 and the depth_ssl options).
+ * clf_default_params fills every field; change what you need. */
+typedef struct clf_params {
+  int32_t precision;        /* CLF_FP64 or CLF_FP32 */
+  double h_min;             /* item ground: flow depth at or below which a node is dry (> 0) */
+  double manning_n2;        /* item crough: Manning n^2; 0 disables friction */
+  int32_t itopo;            /* item itopo: 1 inundation; 0 vertical wall at depth dwall */
+  double dwall;             /* item dwall: nodes shallower than this are land when itopo = 0 */
+  double ssl_alpha;         /* preprocessing limit alpha (dstab); 0 disables it; default 2 */
+  double ssl_min_depth;     /* preprocessing minimal wet depth, default 0.1 m */
+  int32_t sweep_order;      /* CLF_ORDER_XY (default) or CLF_ORDER_ALTERNATE */
+  int32_t solver;           /* 2 = solver2 (default, current Cliffs), 1 = solver1 */
+  double earth_radius;      /* metres, default 6371000 */
+  int32_t spherical_metric; /* 1: tan(lat) continuity source in the y-sweep (default) */
+  double cfl_limit;         /* clf_init fails with CLF_ECFL above this, default 1 */
+  int32_t maxout;           /* item maxout: steps between maxwave updates (>= 1) */
+  int32_t gout;             /* item gout: steps between gauge records (>= 1) */
+  int32_t bndout;           /* item bndout: steps between enclosed-grid records (>= 1) */
+  int32_t max_gauges;       /* capacity: gauges */
+  int32_t gauge_capacity;   /* capacity: gauge records held before clf_clear_records */
+  int32_t max_enclosed;     /* capacity: enclosed grids */
+  int32_t max_enclosed_points; /* capacity: boundary points summed over enclosed grids */
+  int32_t series_capacity;  /* capacity: enclosed-grid records held */
+  int32_t forcing_capacity; /* capacity: time levels per forcing side (0: no forcing) */
+} clf_params;
+
+void clf_default_params(clf_params* p);
+
+/* Device workspace needed by clf_init for this grid and these parameters. */
+int clf_workspace_bytes(const clf_grid* g, const clf_params* p, size_t* bytes);
+
+/* Create a context.  depth: host [ny][nx] (+down, negative = land).  dt: time
+ * step (item dt).  The depth is preprocessed (dstab/newdw/newdc) when
+ * p->ssl_alpha > 0, metric arrays are built, and the still-water Courant
+ * number |lambda| dt / dx (stability remark after solver2) is checked
+ * against p->cfl_limit (CLF_ECFL).  stream: hipStream_t (NULL = default
+ * stream).  ws: device workspace of ws_bytes >= clf_workspace_bytes, owned
+ * by the caller and kept alive until clf_destroy.  The state starts as the
+ * lake at rest. */
+int clf_init(clf_ctx** out, const clf_grid* g, const double* depth, double dt,
+             const clf_params* p, void* stream, void* ws, size_t ws_bytes);
+
+/* Initial conditions (Running Options: input to the computations; item
+ * quake).  eta, u, v: device [ny][nx] FP64 arrays or NULL for zero.  With
+ * deform_bottom = 0 the deformation eta is applied to the free surface
+ * (h = max(d + eta, 0)); with 1 to the sea floor (d <- d - eta, h = max(d, 0)).
+ * Nodes with h <= h_min are dry.  Resets the step counter, maxwave and
+ * records. */
+int clf_set_initial(clf_ctx* c, const double* eta, const double* u, const double* v,
+                    int deform_bottom);
+
+/* Restart: raw state h (water column height), u, v as device [ny][nx] FP64
+ * arrays, and the step index n it belongs to.  clf_get_raw_state then
+ * clf_set_raw_state continues a run bit for bit (FP64). */
+int clf_set_raw_state(clf_ctx* c, const double* h, const double* u, const double* v, int64_t n);
+int clf_get_raw_state(clf_ctx* c, double* h, double* u, double* v);
+
+/* Boundary forcing (Running Options: boundary time-series, layout
+ * vals(tim,uvq,pnt)).  side: CLF_WEST/EAST (np = ny) or CLF_SOUTH/NORTH
+ * (np = nx).  t[nt] strictly increasing model times (host), vals host
+ * [nt][3][np] with uvq = (u, v, eta).  At the start of every step the outer
+ * ring node of that side takes the values interpolated linearly in time at
+ * t = n dt (held constant outside the series) and is not updated by the
+ * sweeps.  Requires p->forcing_capacity >= nt. */
+int clf_set_boundary_forcing(clf_ctx* c, int side, int nt, const double* t, const double* vals);
+
+/* Virtual gauges (items Ngages, gout, and the index list; 0-based here).
+ * ix, iy: host int32 [n].  A record (eta, u, v) of every gauge is taken at
+ * each step index n with n % gout == 0 (including n = 0); dry nodes record
+ * zeros. */
+int clf_set_gauges(clf_ctx* c, int n, const int32_t* ix, const int32_t* iy);
+
+/* Enclosed grid (items nests and the grid names; output boundary series
+ * files).  x[nx], y[ny]: host coordinates inside the master grid.  Every
+ * bndout steps the library records (u, v, eta) along the four sides (W and
+ * E along y, S and N along x) by bilinear interpolation over the wet
+ * corners of the enclosing master cell (all dry: zeros).  *id receives the
+ * grid's index. */
+int clf_add_enclosed_grid(clf_ctx* c, int nx, int ny, const double* x, const double* y, int* id);
+
+/* Advance nsteps split steps (items dt, steps_total).  Asynchronous. */
+int clf_step(clf_ctx* c, int nsteps);
+
+/* One sweep only (axis 0: x-sweep of every row, eq2A; 1: y-sweep of every
+ * column, eq2B), without forcing, sampling or step counting.  Diagnostics. */
+int clf_sweep(clf_ctx* c, int axis);
+
+/* State at the current step: eta = h - d on wet nodes, 0 on dry ones; u, v
+ * (0 on dry nodes); wet = 1 where h > h_min.  Device arrays [ny][nx]; any
+ * may be NULL.  Synchronises the stream. */
+int clf_get_state(clf_ctx* c, double* eta, double* u, double* v, uint8_t* wet);
+
+/* Depth in use (after preprocessing and any sea-floor deformation), device. */
+int clf_get_depth(clf_ctx* c, double* d);
+
+/* Gauge records (output gauges file): host out [nrec][ng][3] (eta, u, v),
+ * times [nrec] = n dt; *nrec receives the count (at most max_rec copied). */
+int clf_read_gauges(clf_ctx* c, double* out, double* times, int* nrec, int max_rec);
+
+/* Maxwave (output maxwave file): running maxima over wet nodes of eta and of
+ * the current speed sqrt(u^2 + v^2), updated after every step n with
+ * n % maxout == 0; both start at 0.  Device [ny][nx] FP64; either may be NULL. */
+int clf_read_maxwave(clf_ctx* c, double* eta_max, double* speed_max);
+
+/* Enclosed-grid series of one side: host vals [nrec][3][np], times [nrec]. */
+int clf_read_boundary_series(clf_ctx* c, int id, int side, double* vals, double* times,
+                             int* nrec, int max_rec);
+
+/* Drop held gauge and enclosed-grid records (capacity is reused). */
+int clf_clear_records(clf_ctx* c);
+
+/* Wait for the stream; report CLF_ENONFINITE if the state went non-finite. */
+int clf_sync(clf_ctx* c);
+
+/* Scalar diagnostics (CLF_Q_*). */
+int clf_query(clf_ctx* c, int what, double* value);
+
+/* Message of the last error on this context (or of the last failed
+ * clf_init when c is NULL).  Valid until the next call on c. */
+const char* clf_last_error(const clf_ctx* c);
+
+/* Free host-side resources.  The workspace stays the caller's. */
+int clf_destroy(clf_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLF_H */

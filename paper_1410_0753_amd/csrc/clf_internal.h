@@ -1,0 +1,127 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// the split-step library.  Not part of the public ABI (include/clf.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace clf {
+
+// node flags inside the sweeps
+enum : int {
+  F_EX = 1,    // node exists (inside the grid)
+  F_WET = 2,   // wet
+  F_FIX = 4,   // forcing ring node: held, not updated by the sweeps
+  F_FLD = 8,   // flooded in step (b) of this sweep
+};
+
+// grid flags
+enum : int {
+  G_FIX_W = 1,
+  G_FIX_E = 2,
+  G_FIX_S = 4,
+  G_FIX_N = 8,
+  G_WALLMODE = 16,  // itopo = 0: nodes shallower than dwall never flood
+  G_SOLVER1 = 32,
+  G_SPHSRC = 64,    // tan(lat) continuity source in the y-sweep
+  G_FRICTION = 128,
+};
+
+// kernel orders
+enum : int { ORD_XY = 0, ORD_YX = 1, ORD_X = 2, ORD_Y = 3 };
+
+// Per-grid descriptor, resident in device memory.  Field arrays are either
+// double (FP64 contexts) or float (FP32 contexts).
+struct GridDesc {
+  int nx, ny;
+  int flags;
+  int maxout;
+  void* H[2];   // FP64: water column height h; FP32: surface eta
+  void* U[2];
+  void* V[2];
+  void* D;      // depth (+down)
+  void* emax;   // running max of eta
+  void* smax2;  // running max of u^2 + v^2
+  const void* xib;   // [nx+1] 1/Delta x_{k-1}
+  const void* xisb;  // [nx]   1/(Delta x_{k-1} + Delta x_k)
+  const void* xfac;  // [ny]   row factor on the x inverse spacings
+  const void* yib;   // [ny+1]
+  const void* yisb;  // [ny]
+  const void* tanR;  // [ny]   tan(lat)/R (zeros when the source is off)
+  double dt, hdt, dt2, hmin, gn2, inv16g, dwall;
+};
+
+// Per-context step counters, resident in device memory.
+struct StepState {
+  long long n;       // time level of the current state
+  unsigned done;     // waves finished in the current step launch
+  int bad;           // non-finite value seen
+  long long g_first; // first gauge record level
+  long long s_first; // first enclosed-grid record level
+};
+
+// Work tile of one wavefront: grid index, first output column, first
+// output row, number of output rows.
+struct Tile {
+  int grid, x0, y0, rows;
+};
+
+// Per-point sampling tables.
+struct SampleDesc {
+  int ngauge;
+  int gout;
+  int npts;          // enclosed-grid boundary points (all grids, all sides)
+  int bndout;
+  const int* gidx;   // [ngauge] node index iy*nx + ix
+  double* grec;      // [cap][ngauge][3]
+  int gcap;
+  const long long* sidx;  // [npts][4] corner node indices
+  const double* swt;      // [npts][4] corner weights
+  const int* sout;        // [npts] offset of the point inside a record: q*np + k within its side block
+  double* srec;           // [cap][rec_len]
+  int rec_len;
+  int scap;
+  int grid;               // grid index in the descriptor table
+};
+
+// Forcing tables (per side).
+struct ForceDesc {
+  int nt[4];
+  int np[4];
+  const double* t[4];
+  const double* vals[4];  // [nt][3][np]
+  int grid;
+};
+
+constexpr int WAVE = 64;
+constexpr int HALO = 3;
+constexpr int STRIP = WAVE - 2 * HALO;  // output columns per wavefront
+constexpr int WAVES_PER_BLOCK = 4;
+
+// Kernel launchers (clf_kernels.hip).
+hipError_t launch_step(int fp32, int order, const GridDesc* grids, const Tile* tiles, int ntiles,
+                       StepState* st, int parity, int count_step, int nblocks, hipStream_t s);
+hipError_t launch_init_state(int fp32, const GridDesc* gd_host, const GridDesc* gd_dev,
+                             const double* eta, const double* u, const double* v, int deform,
+                             long long N, int parity, hipStream_t s);
+hipError_t launch_set_raw(int fp32, const GridDesc* gd_host, const GridDesc* gd_dev,
+                          const double* h, const double* u, const double* v, long long N,
+                          int parity, hipStream_t s);
+hipError_t launch_get_raw(int fp32, const GridDesc* gd_host, const GridDesc* gd_dev, double* h,
+                          double* u, double* v, long long N, int parity, hipStream_t s);
+hipError_t launch_get_state(int fp32, const GridDesc* gd_host, const GridDesc* gd_dev,
+                            double* eta, double* u, double* v, uint8_t* wet, long long N,
+                            int parity, hipStream_t s);
+hipError_t launch_read_maxwave(int fp32, const GridDesc* gd_host, const GridDesc* gd_dev,
+                               double* emax, double* smax, long long N, hipStream_t s);
+hipError_t launch_get_depth(int fp32, const GridDesc* gd_host, const GridDesc* gd_dev, double* d,
+                            long long N, hipStream_t s);
+hipError_t launch_clear_maxwave(int fp32, const GridDesc* gd_host, long long N, hipStream_t s);
+hipError_t launch_sample(int fp32, const GridDesc* gd_dev, const SampleDesc* sd_dev, int nthreads,
+                         StepState* st, int parity, hipStream_t s);
+hipError_t launch_forcing(int fp32, const GridDesc* gd_dev, const ForceDesc* fd_dev, int nthreads,
+                          StepState* st, int parity, hipStream_t s);
+hipError_t launch_deform_depth(int fp32, const GridDesc* gd_host, const double* eta, long long N,
+                               hipStream_t s);
+
+}  // namespace clf

@@ -1,0 +1,944 @@
+// Host runtime and C-ABI of the split-step library (see include/clf.h).
+//
+// Responsibilities: argument validation, the one-time depth preprocessing
+// (section Numerical stability: dstab, newdw, newdc), metric arrays
+// (inverse spacings, spherical row factors and tan(lat)/R), the still-water
+// Courant check (stability remark after solver2), carving of the caller's
+// workspace, the tile list of the march kernel, and the per-step launch
+// sequence (forcing ring -> fused step -> sampling) on the caller's stream.
+
+#include "clf.h"
+#include "clf_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace clf;
+
+namespace {
+
+const bool kHaveFp32Kernels = false;
+const double kGrav = 9.81;
+const double kPiD = 3.14159265358979323846;
+
+thread_local std::string g_init_error;
+
+struct Enc {
+  int nx, ny;
+  int off[4];  // offset of each side block inside a record
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+  size_t gd, st, sd, fd, tiles, f[9], xib, xisb, xfac, yib, yisb, tanR, gidx, grec, sidx, swt,
+      sout, srec, ft[4], fv[4], total;
+  int ntiles_max;
+};
+
+int strips_of(int nx) { return (nx + STRIP - 1) / STRIP; }
+
+constexpr int kMinSeg = 8;
+
+Layout plan(int nx, int ny, const clf_params& p) {
+  Layout L{};
+  const size_t es = p.precision == CLF_FP32 ? 4 : 8;
+  const size_t N = (size_t)nx * ny;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  L.gd = take(sizeof(GridDesc));
+  L.st = take(sizeof(StepState));
+  L.sd = take(sizeof(SampleDesc));
+  L.fd = take(sizeof(ForceDesc));
+  L.ntiles_max = strips_of(nx) * ((ny + kMinSeg - 1) / kMinSeg);
+  L.tiles = take(sizeof(Tile) * (size_t)L.ntiles_max);
+  for (int i = 0; i < 9; ++i) L.f[i] = take(es * N);
+  L.xib = take(es * (nx + 1));
+  L.xisb = take(es * nx);
+  L.xfac = take(es * ny);
+  L.yib = take(es * (ny + 1));
+  L.yisb = take(es * ny);
+  L.tanR = take(es * ny);
+  L.gidx = take(sizeof(int) * std::max(p.max_gauges, 1));
+  L.grec = take(sizeof(double) * 3 * (size_t)std::max(p.max_gauges, 1) *
+                std::max(p.gauge_capacity, 1));
+  const size_t mp = std::max(p.max_enclosed_points, 1);
+  L.sidx = take(sizeof(long long) * 4 * mp);
+  L.swt = take(sizeof(double) * 4 * mp);
+  L.sout = take(sizeof(int) * 2 * mp);
+  L.srec = take(sizeof(double) * 3 * mp * std::max(p.series_capacity, 1));
+  for (int s = 0; s < 4; ++s) {
+    const size_t np = s < 2 ? ny : nx;
+    const size_t fc = std::max(p.forcing_capacity, 0);
+    L.ft[s] = take(sizeof(double) * std::max<size_t>(fc, 1));
+    L.fv[s] = take(sizeof(double) * 3 * np * std::max<size_t>(fc, 1));
+  }
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct clf_ctx {
+  hipStream_t stream = nullptr;
+  int fp32 = 0;
+  int nx = 0, ny = 0, coord = 0;
+  std::vector<double> x, y, d;
+  clf_params p{};
+  double dt = 0;
+  int ssl_passes = 0;
+  double max_cfl = 0, min_f = 0;
+  char* ws = nullptr;
+  Layout L{};
+  GridDesc gd{};
+  GridDesc* gd_dev = nullptr;
+  StepState* st_dev = nullptr;
+  SampleDesc sd{};
+  SampleDesc* sd_dev = nullptr;
+  ForceDesc fd{};
+  ForceDesc* fd_dev = nullptr;
+  Tile* tiles_dev = nullptr;
+  int ntiles = 0, nblocks = 0, seg = 0;
+  bool have_state = false;
+  long long n = 0;
+  int cur = 0;
+  bool rec0 = false;
+  int ngauge = 0;
+  long long g_first = 0;
+  std::vector<Enc> enc;
+  int npts = 0, rec_len = 0;
+  long long s_first = 0;
+  bool forcing = false;
+  std::string err;
+};
+
+namespace {
+
+int fail(clf_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  else g_init_error = buf;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) return fail(ctx, CLF_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+// ----- depth preprocessing: written from dstab / newdw / newdc -----
+// Wet depths under the minimum are raised to it; then Jacobi passes (rows,
+// then columns) replace any wet node whose deeper line neighbour exceeds
+// alpha^2 times its depth: by ((sqrt(d_l) + sqrt(d_r))^2)/4 between two wet
+// neighbours, by d_wet/alpha^2 next to the coast.
+bool ssl_node(double l, double c, double r, double a2, double* out) {
+  if (!(c > 0.0)) return false;
+  const double big = l > r ? l : r;
+  if (!((big / c) > a2)) return false;
+  const bool lw = l > 0.0, rw = r > 0.0;
+  if (lw && rw) {
+    const double s = std::sqrt(l) + std::sqrt(r);
+    *out = (s * s) * 0.25;
+    return true;
+  }
+  if (lw) {
+    *out = l / a2;
+    return true;
+  }
+  if (rw) {
+    *out = r / a2;
+    return true;
+  }
+  return false;
+}
+
+int preprocess_depth(int nx, int ny, std::vector<double>& d, double alpha, double dmin) {
+  for (double& v : d)
+    if (v > 0.0 && v < dmin) v = dmin;
+  const double a2 = alpha * alpha;
+  std::vector<double> nxt(d.size());
+  for (int pass = 1; pass <= 1000; ++pass) {
+    bool moved = false;
+    nxt = d;
+    if (nx >= 3)
+      for (int j = 0; j < ny; ++j) {
+        const double* row = d.data() + (size_t)j * nx;
+        for (int i = 1; i < nx - 1; ++i) {
+          double v;
+          if (ssl_node(row[i - 1], row[i], row[i + 1], a2, &v) && v != row[i]) {
+            nxt[(size_t)j * nx + i] = v;
+            moved = true;
+          }
+        }
+      }
+    d.swap(nxt);
+    nxt = d;
+    if (ny >= 3)
+      for (int j = 1; j < ny - 1; ++j)
+        for (int i = 0; i < nx; ++i) {
+          const size_t k = (size_t)j * nx + i;
+          double v;
+          if (ssl_node(d[k - nx], d[k], d[k + nx], a2, &v) && v != d[k]) {
+            nxt[k] = v;
+            moved = true;
+          }
+        }
+    d.swap(nxt);
+    if (!moved) return pass;
+  }
+  return -1;
+}
+
+// ----- metric arrays -----
+// Along a line with coordinates s and scale q: Delta_k = q (s_{k+1} - s_k),
+// with ghost spacings Delta_{-1} = Delta_0 and Delta_{n-1} = Delta_{n-2}.
+// ib[k] = 1/Delta_{k-1} (k = 0..n), isb[k] = 1/(Delta_{k-1} + Delta_k).
+void line_inverse_spacings(const std::vector<double>& s, double q, std::vector<double>& ib,
+                           std::vector<double>& isb) {
+  const int n = (int)s.size();
+  ib.assign(n + 1, 1.0);
+  isb.assign(n, 1.0);
+  if (n < 2) return;
+  std::vector<double> delta(n + 1);
+  for (int k = 1; k < n; ++k) delta[k] = q * (s[k] - s[k - 1]);
+  delta[0] = delta[1];
+  delta[n] = delta[n - 1];
+  for (int k = 0; k <= n; ++k) ib[k] = 1.0 / delta[k];
+  for (int k = 0; k < n; ++k) isb[k] = 1.0 / (delta[k] + delta[k + 1]);
+}
+
+template <class R>
+hipError_t upload(const std::vector<double>& v, void* dst, hipStream_t s) {
+  std::vector<R> tmp(v.begin(), v.end());
+  hipError_t e = hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+hipError_t upload_any(int fp32, const std::vector<double>& v, void* dst, hipStream_t s) {
+  return fp32 ? upload<float>(v, dst, s) : upload<double>(v, dst, s);
+}
+
+int build_tiles(clf_ctx* c, int seg) {
+  const int ns = strips_of(c->nx);
+  const int nsegs = (c->ny + seg - 1) / seg;
+  std::vector<Tile> t;
+  t.reserve((size_t)ns * nsegs);
+  for (int q = 0; q < nsegs; ++q)
+    for (int s = 0; s < ns; ++s) {
+      Tile tl;
+      tl.grid = 0;
+      tl.x0 = s * STRIP;
+      tl.y0 = q * seg;
+      tl.rows = std::min(seg, c->ny - q * seg);
+      t.push_back(tl);
+    }
+  if ((int)t.size() > c->L.ntiles_max) return fail(c, CLF_EINVAL, "tile list overflow");
+  HIPCHK(c, hipMemcpyAsync(c->tiles_dev, t.data(), t.size() * sizeof(Tile),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->ntiles = (int)t.size();
+  c->nblocks = (c->ntiles + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  c->seg = seg;
+  return CLF_OK;
+}
+
+int default_segment(int nx, int ny) {
+  // enough wavefront tiles to fill 256 CUs several times over, long
+  // segments otherwise (the 6 halo rows of a segment are recomputed)
+  const long long strips = strips_of(nx);
+  int seg = 256;
+  while (seg > 16 && strips * ((ny + seg - 1) / seg) < 4096) seg /= 2;
+  return seg;
+}
+
+int check_ready(clf_ctx* c) {
+  if (!c) return CLF_EINVAL;
+  if (!c->have_state) return fail(c, CLF_ESTATE, "no state: call clf_set_initial first");
+  return CLF_OK;
+}
+
+int sync_and_check(clf_ctx* c) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  StepState st;
+  HIPCHK(c, hipMemcpy(&st, c->st_dev, sizeof st, hipMemcpyDeviceToHost));
+  if (st.bad) return fail(c, CLF_ENONFINITE, "state became non-finite");
+  return CLF_OK;
+}
+
+int push_state(clf_ctx* c) {
+  StepState st{};
+  st.n = c->n;
+  st.done = 0;
+  st.bad = 0;
+  st.g_first = c->g_first;
+  st.s_first = c->s_first;
+  HIPCHK(c, hipMemcpyAsync(c->st_dev, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return CLF_OK;
+}
+
+int push_sampling(clf_ctx* c) {
+  c->sd.ngauge = c->ngauge;
+  c->sd.npts = c->npts;
+  c->sd.rec_len = c->rec_len;
+  HIPCHK(c, hipMemcpyAsync(c->sd_dev, &c->sd, sizeof c->sd, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return CLF_OK;
+}
+
+long long next_level(long long from, int every) {
+  // smallest level >= from that is a multiple of every
+  return (from + every - 1) / every * every;
+}
+
+long long records_between(long long first, int every, long long lo, long long hi) {
+  // number of levels L in [lo, hi] with L >= first and L % every == 0
+  lo = std::max(lo, first);
+  if (hi < lo) return 0;
+  long long a = next_level(lo, every);
+  if (a > hi) return 0;
+  return (hi - a) / every + 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+void clf_default_params(clf_params* p) {
+  std::memset(p, 0, sizeof *p);
+  p->precision = CLF_FP64;
+  p->h_min = 0.1;
+  p->manning_n2 = 0.0;
+  p->itopo = 1;
+  p->dwall = 0.0;
+  p->ssl_alpha = 2.0;
+  p->ssl_min_depth = 0.1;
+  p->sweep_order = CLF_ORDER_XY;
+  p->solver = 2;
+  p->earth_radius = 6371000.0;
+  p->spherical_metric = 1;
+  p->cfl_limit = 1.0;
+  p->maxout = 1;
+  p->gout = 1;
+  p->bndout = 1;
+  p->max_gauges = 64;
+  p->gauge_capacity = 4096;
+  p->max_enclosed = 4;
+  p->max_enclosed_points = 4 * 2 * (400 + 400);
+  p->series_capacity = 64;
+  p->forcing_capacity = 0;
+}
+
+static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c) {
+  if (!g || !p) return fail(c, CLF_EINVAL, "null grid or params");
+  if (g->nx < 1 || g->ny < 1) return fail(c, CLF_EINVAL, "nx, ny must be >= 1");
+  const bool oned = g->nx == 1 || g->ny == 1;
+  if (oned && (long long)g->nx * g->ny < 3)
+    return fail(c, CLF_EINVAL, "a 1-D grid needs at least 3 nodes");
+  if (!oned && (g->nx < 3 || g->ny < 3))
+    return fail(c, CLF_EINVAL, "a 2-D grid needs at least 3 nodes per direction");
+  if (g->coord != CLF_CARTESIAN && g->coord != CLF_SPHERICAL)
+    return fail(c, CLF_EINVAL, "bad coordinate system");
+  if (!g->x || !g->y) return fail(c, CLF_EINVAL, "null coordinates");
+  for (int i = 0; i + 1 < g->nx; ++i)
+    if (!(g->x[i + 1] > g->x[i])) return fail(c, CLF_EINVAL, "x not strictly increasing");
+  for (int j = 0; j + 1 < g->ny; ++j)
+    if (!(g->y[j + 1] > g->y[j])) return fail(c, CLF_EINVAL, "y not strictly increasing");
+  if (g->coord == CLF_SPHERICAL)
+    for (int j = 0; j < g->ny; ++j)
+      if (!(std::fabs(g->y[j]) < 89.9)) return fail(c, CLF_EINVAL, "latitude out of range");
+  if (p->precision != CLF_FP64 && p->precision != CLF_FP32)
+    return fail(c, CLF_EINVAL, "bad precision");
+  if (p->precision == CLF_FP32 && !kHaveFp32Kernels)
+    return fail(c, CLF_EINVAL, "FP32 kernels are not built into this library");
+  if (!(p->h_min > 0.0)) return fail(c, CLF_EINVAL, "h_min must be > 0");
+  if (p->manning_n2 < 0.0) return fail(c, CLF_EINVAL, "manning_n2 must be >= 0");
+  if (p->solver != 1 && p->solver != 2) return fail(c, CLF_EINVAL, "solver must be 1 or 2");
+  if (p->sweep_order != CLF_ORDER_XY && p->sweep_order != CLF_ORDER_ALTERNATE)
+    return fail(c, CLF_EINVAL, "bad sweep order");
+  if (p->maxout < 1 || p->gout < 1 || p->bndout < 1)
+    return fail(c, CLF_EINVAL, "maxout, gout, bndout must be >= 1");
+  if (p->ssl_alpha < 0.0 || (p->ssl_alpha > 0.0 && !(p->ssl_alpha > 1.0)))
+    return fail(c, CLF_EINVAL, "ssl_alpha must be 0 (off) or > 1");
+  if (p->max_gauges < 0 || p->gauge_capacity < 0 || p->max_enclosed < 0 ||
+      p->max_enclosed_points < 0 || p->series_capacity < 0 || p->forcing_capacity < 0)
+    return fail(c, CLF_EINVAL, "negative capacity");
+  if (p->earth_radius <= 0.0) return fail(c, CLF_EINVAL, "earth_radius must be > 0");
+  return CLF_OK;
+}
+
+int clf_workspace_bytes(const clf_grid* g, const clf_params* p, size_t* bytes) {
+  int rc = validate(g, p, nullptr);
+  if (rc) return rc;
+  if (!bytes) return fail(nullptr, CLF_EINVAL, "null output");
+  *bytes = plan(g->nx, g->ny, *p).total;
+  return CLF_OK;
+}
+
+int clf_init(clf_ctx** out, const clf_grid* g, const double* depth, double dt,
+             const clf_params* p, void* stream, void* ws, size_t ws_bytes) {
+  if (!out) return fail(nullptr, CLF_EINVAL, "null output");
+  *out = nullptr;
+  int rc = validate(g, p, nullptr);
+  if (rc) return rc;
+  if (!depth) return fail(nullptr, CLF_EINVAL, "null depth");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(nullptr, CLF_EINVAL, "dt must be > 0");
+  if (!ws) return fail(nullptr, CLF_EINVAL, "null workspace");
+  Layout L = plan(g->nx, g->ny, *p);
+  if (ws_bytes < L.total)
+    return fail(nullptr, CLF_ENOSPACE, "workspace too small: %zu < %zu", ws_bytes, L.total);
+  if (((uintptr_t)ws) % 256 != 0) return fail(nullptr, CLF_EINVAL, "workspace not 256-B aligned");
+
+  clf_ctx* c = new clf_ctx();
+  c->stream = (hipStream_t)stream;
+  c->p = *p;
+  c->fp32 = p->precision == CLF_FP32;
+  c->nx = g->nx;
+  c->ny = g->ny;
+  c->coord = g->coord;
+  c->x.assign(g->x, g->x + g->nx);
+  c->y.assign(g->y, g->y + g->ny);
+  const size_t N = (size_t)c->nx * c->ny;
+  c->d.assign(depth, depth + N);
+  for (size_t k = 0; k < N; ++k)
+    if (!std::isfinite(c->d[k])) {
+      delete c;
+      return fail(nullptr, CLF_EINVAL, "non-finite depth");
+    }
+  c->dt = dt;
+  c->ws = (char*)ws;
+  c->L = L;
+
+  if (p->ssl_alpha > 0.0) {
+    c->ssl_passes = preprocess_depth(c->nx, c->ny, c->d, p->ssl_alpha, p->ssl_min_depth);
+    if (c->ssl_passes < 0) {
+      delete c;
+      return fail(nullptr, CLF_ESSL, "depth preprocessing did not converge in 1000 passes");
+    }
+  }
+
+  // metrics
+  std::vector<double> xib, xisb, yib, yisb, xfac(c->ny, 1.0), tanR(c->ny, 0.0);
+  const double deg = kPiD / 180.0;
+  int flags = 0;
+  if (c->coord == CLF_SPHERICAL) {
+    const double Rd = p->earth_radius * deg;
+    line_inverse_spacings(c->x, 1.0, xib, xisb);
+    for (int j = 0; j < c->ny; ++j) xfac[j] = 1.0 / (Rd * std::cos(c->y[j] * deg));
+    line_inverse_spacings(c->y, Rd, yib, yisb);
+    if (p->spherical_metric) {
+      for (int j = 0; j < c->ny; ++j) tanR[j] = std::tan(c->y[j] * deg) / p->earth_radius;
+      flags |= G_SPHSRC;
+    }
+  } else {
+    line_inverse_spacings(c->x, 1.0, xib, xisb);
+    line_inverse_spacings(c->y, 1.0, yib, yisb);
+  }
+
+  // still-water Courant number over wet nodes, and min f_j (eq:f)
+  double cmax = 0.0, fmin = 1e300;
+  for (int j = 0; j < c->ny; ++j)
+    for (int i = 0; i < c->nx; ++i) {
+      const double dd = c->d[(size_t)j * c->nx + i];
+      if (!(dd > 0.0)) continue;
+      const double cs = std::sqrt(kGrav * dd) * dt;
+      if (c->nx > 1) cmax = std::max(cmax, cs * xfac[j] * std::max(xib[i], xib[i + 1]));
+      if (c->ny > 1) cmax = std::max(cmax, cs * std::max(yib[j], yib[j + 1]));
+      auto fj = [&](double l, double r) {
+        if (l > 0.0 && r > 0.0)
+          fmin = std::min(fmin, (6.0 * std::sqrt(dd) - std::sqrt(l) - std::sqrt(r)) /
+                                    (4.0 * std::sqrt(dd)));
+      };
+      if (i > 0 && i + 1 < c->nx) fj(c->d[(size_t)j * c->nx + i - 1], c->d[(size_t)j * c->nx + i + 1]);
+      if (j > 0 && j + 1 < c->ny) fj(c->d[(size_t)(j - 1) * c->nx + i], c->d[(size_t)(j + 1) * c->nx + i]);
+    }
+  c->max_cfl = cmax;
+  c->min_f = fmin;
+  if (cmax > p->cfl_limit) {
+    delete c;
+    return fail(nullptr, CLF_ECFL, "still-water Courant number %.4f exceeds %.4f", cmax,
+                p->cfl_limit);
+  }
+
+  // carve the workspace
+  char* b = c->ws;
+  c->gd_dev = (GridDesc*)(b + L.gd);
+  c->st_dev = (StepState*)(b + L.st);
+  c->sd_dev = (SampleDesc*)(b + L.sd);
+  c->fd_dev = (ForceDesc*)(b + L.fd);
+  c->tiles_dev = (Tile*)(b + L.tiles);
+  GridDesc& gd = c->gd;
+  gd.nx = c->nx;
+  gd.ny = c->ny;
+  if (p->itopo == 0) flags |= G_WALLMODE;
+  if (p->solver == 1) flags |= G_SOLVER1;
+  if (p->manning_n2 > 0.0) flags |= G_FRICTION;
+  gd.flags = flags;
+  gd.maxout = p->maxout;
+  gd.H[0] = b + L.f[0]; gd.H[1] = b + L.f[1];
+  gd.U[0] = b + L.f[2]; gd.U[1] = b + L.f[3];
+  gd.V[0] = b + L.f[4]; gd.V[1] = b + L.f[5];
+  gd.D = b + L.f[6];
+  gd.emax = b + L.f[7];
+  gd.smax2 = b + L.f[8];
+  gd.xib = b + L.xib;
+  gd.xisb = b + L.xisb;
+  gd.xfac = b + L.xfac;
+  gd.yib = b + L.yib;
+  gd.yisb = b + L.yisb;
+  gd.tanR = b + L.tanR;
+  gd.dt = dt;
+  gd.hdt = 0.5 * dt;
+  gd.dt2 = dt * dt;
+  gd.hmin = p->h_min;
+  gd.gn2 = kGrav * p->manning_n2;
+  gd.inv16g = 1.0 / (16.0 * kGrav);
+  gd.dwall = p->dwall;
+
+  hipStream_t s = c->stream;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = upload_any(c->fp32, c->d, (void*)gd.D, s);
+  if (e == hipSuccess) e = upload_any(c->fp32, xib, (void*)gd.xib, s);
+  if (e == hipSuccess) e = upload_any(c->fp32, xisb, (void*)gd.xisb, s);
+  if (e == hipSuccess) e = upload_any(c->fp32, xfac, (void*)gd.xfac, s);
+  if (e == hipSuccess) e = upload_any(c->fp32, yib, (void*)gd.yib, s);
+  if (e == hipSuccess) e = upload_any(c->fp32, yisb, (void*)gd.yisb, s);
+  if (e == hipSuccess) e = upload_any(c->fp32, tanR, (void*)gd.tanR, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->gd_dev, &gd, sizeof gd, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    std::string m = hipGetErrorString(e);
+    delete c;
+    return fail(nullptr, CLF_EHIP, "upload failed: %s", m.c_str());
+  }
+
+  // sampling and forcing tables
+  c->sd = SampleDesc{};
+  c->sd.gout = p->gout;
+  c->sd.bndout = p->bndout;
+  c->sd.gidx = (const int*)(b + L.gidx);
+  c->sd.grec = (double*)(b + L.grec);
+  c->sd.gcap = p->gauge_capacity;
+  c->sd.sidx = (const long long*)(b + L.sidx);
+  c->sd.swt = (const double*)(b + L.swt);
+  c->sd.sout = (const int*)(b + L.sout);
+  c->sd.srec = (double*)(b + L.srec);
+  c->sd.scap = p->series_capacity;
+  c->sd.grid = 0;
+  c->fd = ForceDesc{};
+  c->fd.grid = 0;
+  for (int sd = 0; sd < 4; ++sd) {
+    c->fd.t[sd] = (const double*)(b + L.ft[sd]);
+    c->fd.vals[sd] = (const double*)(b + L.fv[sd]);
+  }
+  int r2 = push_sampling(c);
+  if (r2 == CLF_OK) {
+    hipError_t e2 = hipMemcpyAsync(c->fd_dev, &c->fd, sizeof c->fd, hipMemcpyHostToDevice, s);
+    if (e2 != hipSuccess) r2 = fail(c, CLF_EHIP, "forcing table upload failed");
+  }
+  if (r2 == CLF_OK) r2 = build_tiles(c, default_segment(c->nx, c->ny));
+  if (r2 == CLF_OK) {
+    // lake at rest: h = max(d, 0), dry at or below h_min
+    c->have_state = true;
+    r2 = clf_set_initial(c, nullptr, nullptr, nullptr, 0);
+  }
+  if (r2 != CLF_OK) {
+    g_init_error = c->err;
+    delete c;
+    return r2;
+  }
+  *out = c;
+  return CLF_OK;
+}
+
+int clf_set_initial(clf_ctx* c, const double* eta, const double* u, const double* v,
+                    int deform_bottom) {
+  if (!c) return CLF_EINVAL;
+  const long long N = (long long)c->nx * c->ny;
+  c->cur = 0;
+  HIPCHK(c, launch_init_state(c->fp32, &c->gd, c->gd_dev, eta, u, v, deform_bottom ? 1 : 0, N,
+                              c->cur, c->stream));
+  HIPCHK(c, launch_clear_maxwave(c->fp32, &c->gd, N, c->stream));
+  c->have_state = true;
+  c->n = 0;
+  c->rec0 = false;
+  c->g_first = 0;
+  c->s_first = 0;
+  return push_state(c);
+}
+
+int clf_set_raw_state(clf_ctx* c, const double* h, const double* u, const double* v, int64_t n) {
+  if (!c) return CLF_EINVAL;
+  if (!h || !u || !v) return fail(c, CLF_EINVAL, "raw state needs h, u and v");
+  if (n < 0) return fail(c, CLF_EINVAL, "negative step index");
+  const long long N = (long long)c->nx * c->ny;
+  c->cur = 0;
+  HIPCHK(c, launch_set_raw(c->fp32, &c->gd, c->gd_dev, h, u, v, N, c->cur, c->stream));
+  c->have_state = true;
+  c->n = n;
+  c->rec0 = n > 0;  // the record of level n was taken by the run that reached it
+  c->g_first = next_level(c->rec0 ? n + 1 : n, c->p.gout);
+  c->s_first = next_level(c->rec0 ? n + 1 : n, c->p.bndout);
+  return push_state(c);
+}
+
+int clf_get_raw_state(clf_ctx* c, double* h, double* u, double* v) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  const long long N = (long long)c->nx * c->ny;
+  HIPCHK(c, launch_get_raw(c->fp32, &c->gd, c->gd_dev, h, u, v, N, c->cur, c->stream));
+  return sync_and_check(c);
+}
+
+int clf_set_boundary_forcing(clf_ctx* c, int side, int nt, const double* t, const double* vals) {
+  if (!c) return CLF_EINVAL;
+  if (side < 0 || side > 3) return fail(c, CLF_EINVAL, "bad side");
+  if ((c->nx == 1 && side < 2) || (c->ny == 1 && side >= 2))
+    return fail(c, CLF_EINVAL, "side not present on this 1-D grid");
+  if (nt < 1 || !t || !vals) return fail(c, CLF_EINVAL, "empty forcing series");
+  if (nt > c->p.forcing_capacity)
+    return fail(c, CLF_ENOSPACE, "forcing series of %d levels exceeds forcing_capacity %d", nt,
+                c->p.forcing_capacity);
+  for (int k = 0; k + 1 < nt; ++k)
+    if (!(t[k + 1] > t[k])) return fail(c, CLF_EINVAL, "forcing times not increasing");
+  const int np = side < 2 ? c->ny : c->nx;
+  HIPCHK(c, hipMemcpyAsync((void*)c->fd.t[side], t, sizeof(double) * nt, hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync((void*)c->fd.vals[side], vals, sizeof(double) * 3 * np * (size_t)nt,
+                           hipMemcpyHostToDevice, c->stream));
+  c->fd.nt[side] = nt;
+  c->fd.np[side] = np;
+  HIPCHK(c, hipMemcpyAsync(c->fd_dev, &c->fd, sizeof c->fd, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int bit[4] = {G_FIX_W, G_FIX_E, G_FIX_S, G_FIX_N};
+  c->gd.flags |= bit[side];
+  HIPCHK(c, hipMemcpyAsync(c->gd_dev, &c->gd, sizeof c->gd, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->forcing = true;
+  return CLF_OK;
+}
+
+int clf_set_gauges(clf_ctx* c, int n, const int32_t* ix, const int32_t* iy) {
+  if (!c) return CLF_EINVAL;
+  if (n < 0 || n > c->p.max_gauges)
+    return fail(c, CLF_ENOSPACE, "%d gauges exceed max_gauges %d", n, c->p.max_gauges);
+  if (n > 0 && (!ix || !iy)) return fail(c, CLF_EINVAL, "null gauge index");
+  std::vector<int> idx(n);
+  for (int g = 0; g < n; ++g) {
+    if (ix[g] < 0 || ix[g] >= c->nx || iy[g] < 0 || iy[g] >= c->ny)
+      return fail(c, CLF_EINVAL, "gauge %d outside the grid", g);
+    idx[g] = iy[g] * c->nx + ix[g];
+  }
+  if (n > 0)
+    HIPCHK(c, hipMemcpyAsync((void*)c->sd.gidx, idx.data(), sizeof(int) * n,
+                             hipMemcpyHostToDevice, c->stream));
+  c->ngauge = n;
+  // records restart at the current level (or at 0 before the first step)
+  c->g_first = c->rec0 ? next_level(c->n + 1, c->p.gout) : next_level(c->n, c->p.gout);
+  int rc = push_sampling(c);
+  if (rc) return rc;
+  StepState st{};
+  HIPCHK(c, hipMemcpy(&st, c->st_dev, sizeof st, hipMemcpyDeviceToHost));
+  st.g_first = c->g_first;
+  HIPCHK(c, hipMemcpy(c->st_dev, &st, sizeof st, hipMemcpyHostToDevice));
+  return CLF_OK;
+}
+
+int clf_add_enclosed_grid(clf_ctx* c, int nx, int ny, const double* x, const double* y, int* id) {
+  if (!c) return CLF_EINVAL;
+  if (c->nx == 1 || c->ny == 1) return fail(c, CLF_EINVAL, "nesting is not enabled for 1-D grids");
+  if (nx < 2 || ny < 2 || !x || !y) return fail(c, CLF_EINVAL, "bad enclosed grid");
+  if ((int)c->enc.size() >= c->p.max_enclosed)
+    return fail(c, CLF_ENOSPACE, "more than max_enclosed enclosed grids");
+  const int pts = 2 * (nx + ny);
+  if (c->npts + pts > c->p.max_enclosed_points)
+    return fail(c, CLF_ENOSPACE, "enclosed boundary points exceed max_enclosed_points");
+  auto locate = [](const std::vector<double>& cc, double pnt, int* i0, double* w) -> bool {
+    const int n = (int)cc.size();
+    if (!(pnt >= cc[0] && pnt <= cc[n - 1])) return false;
+    // largest i <= n-2 with cc[i] <= pnt
+    int lo = 0, hi = n - 1;
+    while (hi - lo > 1) {
+      int mid = (lo + hi) / 2;
+      if (cc[mid] <= pnt) lo = mid;
+      else hi = mid;
+    }
+    *i0 = lo;
+    *w = (pnt - cc[lo]) / (cc[lo + 1] - cc[lo]);
+    return true;
+  };
+  std::vector<long long> sidx((size_t)4 * pts);
+  std::vector<double> swt((size_t)4 * pts);
+  std::vector<int> off(pts), stride(pts);
+  Enc E;
+  E.nx = nx;
+  E.ny = ny;
+  int o = c->rec_len, q = 0;
+  for (int s = 0; s < 4; ++s) {
+    const int np = s < 2 ? ny : nx;
+    E.off[s] = o;
+    for (int k = 0; k < np; ++k, ++q) {
+      double px, py;
+      if (s == 0) { px = x[0]; py = y[k]; }
+      else if (s == 1) { px = x[nx - 1]; py = y[k]; }
+      else if (s == 2) { px = x[k]; py = y[0]; }
+      else { px = x[k]; py = y[ny - 1]; }
+      int i0, j0;
+      double wx, wy;
+      if (!locate(c->x, px, &i0, &wx) || !locate(c->y, py, &j0, &wy))
+        return fail(c, CLF_EINVAL, "enclosed grid point outside the master grid");
+      const long long base = (long long)j0 * c->nx + i0;
+      const long long id4[4] = {base, base + 1, base + c->nx, base + c->nx + 1};
+      const double w4[4] = {(1.0 - wx) * (1.0 - wy), wx * (1.0 - wy), (1.0 - wx) * wy, wx * wy};
+      for (int cc = 0; cc < 4; ++cc) {
+        sidx[(size_t)4 * q + cc] = id4[cc];
+        swt[(size_t)4 * q + cc] = w4[cc];
+      }
+      off[q] = o + k;
+      stride[q] = np;
+    }
+    o += 3 * np;
+  }
+  // all points of all grids live in one table; append this grid's rows
+  const int p0 = c->npts;
+  HIPCHK(c, hipMemcpyAsync((void*)(c->sd.sidx + (size_t)4 * p0), sidx.data(),
+                           sizeof(long long) * sidx.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync((void*)(c->sd.swt + (size_t)4 * p0), swt.data(),
+                           sizeof(double) * swt.size(), hipMemcpyHostToDevice, c->stream));
+  // sout = [off of all points..., stride of all points...]: rebuild whole table
+  std::vector<int> sout_all((size_t)2 * (p0 + pts));
+  if (p0 > 0)
+    HIPCHK(c, hipMemcpy(sout_all.data(), c->sd.sout, sizeof(int) * 2 * p0, hipMemcpyDeviceToHost));
+  std::vector<int> rebuilt((size_t)2 * (p0 + pts));
+  for (int i = 0; i < p0; ++i) {
+    rebuilt[i] = sout_all[i];
+    rebuilt[(size_t)p0 + pts + i] = sout_all[(size_t)p0 + i];
+  }
+  for (int i = 0; i < pts; ++i) {
+    rebuilt[(size_t)p0 + i] = off[i];
+    rebuilt[(size_t)2 * p0 + pts + i] = stride[i];
+  }
+  HIPCHK(c, hipMemcpyAsync((void*)c->sd.sout, rebuilt.data(), sizeof(int) * rebuilt.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  c->npts += pts;
+  c->rec_len = o;
+  c->enc.push_back(E);
+  c->s_first = c->rec0 ? next_level(c->n + 1, c->p.bndout) : next_level(c->n, c->p.bndout);
+  int rc = push_sampling(c);
+  if (rc) return rc;
+  StepState st{};
+  HIPCHK(c, hipMemcpy(&st, c->st_dev, sizeof st, hipMemcpyDeviceToHost));
+  st.s_first = c->s_first;
+  HIPCHK(c, hipMemcpy(c->st_dev, &st, sizeof st, hipMemcpyHostToDevice));
+  if (id) *id = (int)c->enc.size() - 1;
+  return CLF_OK;
+}
+
+static int launch_sampling(clf_ctx* c) {
+  if (c->ngauge == 0 && c->npts == 0) return CLF_OK;
+  const int nthr = std::max(c->ngauge, c->npts);
+  HIPCHK(c, launch_sample(c->fp32, c->gd_dev, c->sd_dev, nthr, c->st_dev, c->cur, c->stream));
+  return CLF_OK;
+}
+
+static int step_order(clf_ctx* c) {
+  if (c->ny == 1) return ORD_X;
+  if (c->nx == 1) return ORD_Y;
+  if (c->p.sweep_order == CLF_ORDER_ALTERNATE && (c->n % 2) == 1) return ORD_YX;
+  return ORD_XY;
+}
+
+int clf_step(clf_ctx* c, int nsteps) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (nsteps < 0) return fail(c, CLF_EINVAL, "negative step count");
+  if (nsteps == 0) return CLF_OK;
+  // record capacity for levels [first pending, n + nsteps]
+  const long long lo = c->rec0 ? c->n + 1 : c->n;
+  const long long hi = c->n + nsteps;
+  if (c->ngauge > 0) {
+    const long long need = records_between(c->g_first, c->p.gout, c->g_first, hi);
+    if (need > c->p.gauge_capacity)
+      return fail(c, CLF_ENOSPACE, "gauge records would exceed gauge_capacity (%lld > %d)", need,
+                  c->p.gauge_capacity);
+  }
+  if (c->npts > 0) {
+    const long long need = records_between(c->s_first, c->p.bndout, c->s_first, hi);
+    if (need > c->p.series_capacity)
+      return fail(c, CLF_ENOSPACE, "series records would exceed series_capacity (%lld > %d)",
+                  need, c->p.series_capacity);
+  }
+  (void)lo;
+  if (!c->rec0) {
+    rc = launch_sampling(c);
+    if (rc) return rc;
+    c->rec0 = true;
+  }
+  for (int k = 0; k < nsteps; ++k) {
+    if (c->forcing)
+      HIPCHK(c, launch_forcing(c->fp32, c->gd_dev, c->fd_dev, std::max(c->nx, c->ny), c->st_dev,
+                               c->cur, c->stream));
+    HIPCHK(c, launch_step(c->fp32, step_order(c), c->gd_dev, c->tiles_dev, c->ntiles, c->st_dev,
+                          c->cur, 1, c->nblocks, c->stream));
+    c->cur ^= 1;
+    c->n += 1;
+    rc = launch_sampling(c);
+    if (rc) return rc;
+  }
+  return CLF_OK;
+}
+
+int clf_sweep(clf_ctx* c, int axis) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (axis != 0 && axis != 1) return fail(c, CLF_EINVAL, "axis must be 0 or 1");
+  if ((axis == 0 && c->nx == 1) || (axis == 1 && c->ny == 1))
+    return fail(c, CLF_EINVAL, "no sweep along a dimension of length 1");
+  HIPCHK(c, launch_step(c->fp32, axis == 0 ? ORD_X : ORD_Y, c->gd_dev, c->tiles_dev, c->ntiles,
+                        c->st_dev, c->cur, 0, c->nblocks, c->stream));
+  c->cur ^= 1;
+  return CLF_OK;
+}
+
+int clf_get_state(clf_ctx* c, double* eta, double* u, double* v, uint8_t* wet) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  const long long N = (long long)c->nx * c->ny;
+  HIPCHK(c, launch_get_state(c->fp32, &c->gd, c->gd_dev, eta, u, v, wet, N, c->cur, c->stream));
+  return sync_and_check(c);
+}
+
+int clf_get_depth(clf_ctx* c, double* d) {
+  if (!c || !d) return CLF_EINVAL;
+  const long long N = (long long)c->nx * c->ny;
+  HIPCHK(c, launch_get_depth(c->fp32, &c->gd, c->gd_dev, d, N, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return CLF_OK;
+}
+
+int clf_read_gauges(clf_ctx* c, double* out, double* times, int* nrec, int max_rec) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  rc = sync_and_check(c);
+  if (rc) return rc;
+  long long have = 0;
+  if (c->ngauge > 0 && c->rec0)
+    have = records_between(c->g_first, c->p.gout, c->g_first, c->n);
+  have = std::min<long long>(have, c->p.gauge_capacity);
+  if (nrec) *nrec = (int)have;
+  const long long cp = std::min<long long>(have, std::max(max_rec, 0));
+  if (cp > 0 && out)
+    HIPCHK(c, hipMemcpy(out, c->sd.grec, sizeof(double) * 3 * c->ngauge * cp,
+                        hipMemcpyDeviceToHost));
+  if (times)
+    for (long long r = 0; r < cp; ++r)
+      times[r] = (double)(c->g_first + r * c->p.gout) * c->dt;
+  return CLF_OK;
+}
+
+int clf_read_maxwave(clf_ctx* c, double* eta_max, double* speed_max) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  const long long N = (long long)c->nx * c->ny;
+  HIPCHK(c, launch_read_maxwave(c->fp32, &c->gd, c->gd_dev, eta_max, speed_max, N, c->stream));
+  return sync_and_check(c);
+}
+
+int clf_read_boundary_series(clf_ctx* c, int id, int side, double* vals, double* times,
+                             int* nrec, int max_rec) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (id < 0 || id >= (int)c->enc.size()) return fail(c, CLF_EINVAL, "bad enclosed grid id");
+  if (side < 0 || side > 3) return fail(c, CLF_EINVAL, "bad side");
+  rc = sync_and_check(c);
+  if (rc) return rc;
+  long long have = 0;
+  if (c->rec0) have = records_between(c->s_first, c->p.bndout, c->s_first, c->n);
+  have = std::min<long long>(have, c->p.series_capacity);
+  if (nrec) *nrec = (int)have;
+  const long long cp = std::min<long long>(have, std::max(max_rec, 0));
+  const Enc& E = c->enc[id];
+  const int np = side < 2 ? E.ny : E.nx;
+  if (cp > 0 && vals) {
+    std::vector<double> rec((size_t)c->rec_len);
+    for (long long r = 0; r < cp; ++r) {
+      HIPCHK(c, hipMemcpy(vals + (size_t)r * 3 * np,
+                          c->sd.srec + (size_t)r * c->rec_len + E.off[side],
+                          sizeof(double) * 3 * np, hipMemcpyDeviceToHost));
+    }
+  }
+  if (times)
+    for (long long r = 0; r < cp; ++r)
+      times[r] = (double)(c->s_first + r * c->p.bndout) * c->dt;
+  return CLF_OK;
+}
+
+int clf_clear_records(clf_ctx* c) {
+  if (!c) return CLF_EINVAL;
+  const long long from = c->rec0 ? c->n + 1 : c->n;
+  c->g_first = next_level(from, c->p.gout);
+  c->s_first = next_level(from, c->p.bndout);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  StepState st{};
+  HIPCHK(c, hipMemcpy(&st, c->st_dev, sizeof st, hipMemcpyDeviceToHost));
+  st.g_first = c->g_first;
+  st.s_first = c->s_first;
+  HIPCHK(c, hipMemcpy(c->st_dev, &st, sizeof st, hipMemcpyHostToDevice));
+  return CLF_OK;
+}
+
+int clf_sync(clf_ctx* c) {
+  if (!c) return CLF_EINVAL;
+  return sync_and_check(c);
+}
+
+int clf_query(clf_ctx* c, int what, double* value) {
+  if (!c || !value) return CLF_EINVAL;
+  switch (what) {
+    case CLF_Q_MAX_CFL: *value = c->max_cfl; break;
+    case CLF_Q_SSL_PASSES: *value = c->ssl_passes; break;
+    case CLF_Q_STEP: *value = (double)c->n; break;
+    case CLF_Q_MIN_F: *value = c->min_f; break;
+    case CLF_Q_WORKSPACE: *value = (double)c->L.total; break;
+    case CLF_Q_GAUGE_RECORDS: {
+      long long have = 0;
+      if (c->ngauge > 0 && c->rec0) have = records_between(c->g_first, c->p.gout, c->g_first, c->n);
+      *value = (double)have;
+      break;
+    }
+    case CLF_Q_TILES: *value = c->ntiles; break;
+    case CLF_Q_SEGMENT: *value = c->seg; break;
+    default: return fail(c, CLF_EINVAL, "unknown query %d", what);
+  }
+  return CLF_OK;
+}
+
+const char* clf_last_error(const clf_ctx* c) {
+  return c ? c->err.c_str() : g_init_error.c_str();
+}
+
+int clf_destroy(clf_ctx* c) {
+  if (!c) return CLF_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  delete c;
+  return CLF_OK;
+}
+
+}  // extern "C"
