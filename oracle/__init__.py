@@ -102,7 +102,15 @@ class Oracle:
     def __init__(self, x, y, depth, dt, coord=CARTESIAN, h_min=0.1, manning_n2=0.0,
                  itopo=1, dwall=0.0, ssl_alpha=2.0, ssl_min_depth=0.1, order=ORDER_XY,
                  solver=2, earth_radius=R_EARTH, spherical_metric=1, maxout=1, gout=1,
-                 bndout=1):
+                 bndout=1, sweep_order=None, **device_only):
+        # capacities and limits of the GPU library have no meaning here
+        unknown = set(device_only) - {"precision", "cfl_limit", "max_gauges", "gauge_capacity",
+                                      "max_enclosed", "max_enclosed_points", "series_capacity",
+                                      "forcing_capacity"}
+        if unknown:
+            raise TypeError("unknown oracle parameter(s) %s" % sorted(unknown))
+        if sweep_order is not None:
+            order = sweep_order
         L = lib()
         depth = _f64(depth)
         self.ny, self.nx = depth.shape
@@ -119,8 +127,8 @@ class Oracle:
 
     @classmethod
     def from_case(cls, case, **kw):
-        o = cls(case.x, case.y, case.depth, case.dt, coord=case.coord, h_min=case.h_min, **kw)
-        return o
+        kw.setdefault("h_min", case.h_min)
+        return cls(case.x, case.y, case.depth, case.dt, coord=case.coord, **kw)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -159,7 +159,8 @@ class Solver:
 
     @classmethod
     def from_case(cls, case, **kw):
-        return cls(case.x, case.y, case.depth, case.dt, coord=case.coord, h_min=case.h_min, **kw)
+        kw.setdefault("h_min", case.h_min)
+        return cls(case.x, case.y, case.depth, case.dt, coord=case.coord, **kw)
 
     # -- errors --
     def _check_init(self, rc):
