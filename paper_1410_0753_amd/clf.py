@@ -52,7 +52,8 @@ class Params(C.Structure):
                 ("cfl_limit", C.c_double), ("maxout", C.c_int32), ("gout", C.c_int32),
                 ("bndout", C.c_int32), ("max_gauges", C.c_int32), ("gauge_capacity", C.c_int32),
                 ("max_enclosed", C.c_int32), ("max_enclosed_points", C.c_int32),
-                ("series_capacity", C.c_int32), ("forcing_capacity", C.c_int32)]
+                ("series_capacity", C.c_int32), ("forcing_capacity", C.c_int32),
+                ("segment", C.c_int32), ("autotune", C.c_int32)]
 
 
 _lock = threading.Lock()
@@ -173,8 +174,8 @@ class Solver:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            load().clf_destroy(h)
+        if h and _lib is not None:
+            _lib.clf_destroy(h)
             self._h = None
 
     # -- helpers --

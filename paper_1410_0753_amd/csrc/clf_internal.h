@@ -51,13 +51,10 @@ struct GridDesc {
   double dt, hdt, dt2, hmin, gn2, inv16g, dwall;
 };
 
-// Per-context step counters, resident in device memory.
+// Per-context device flags.
 struct StepState {
-  long long n;       // time level of the current state
-  unsigned done;     // waves finished in the current step launch
-  int bad;           // non-finite value seen
-  long long g_first; // first gauge record level
-  long long s_first; // first enclosed-grid record level
+  int bad;           // a non-finite value was written
+  int pad[3];
 };
 
 // Work tile of one wavefront: grid index, first output column, first
@@ -82,6 +79,8 @@ struct SampleDesc {
   int rec_len;
   int scap;
   int grid;               // grid index in the descriptor table
+  long long g_first;      // first gauge record level
+  long long s_first;      // first enclosed-grid record level
 };
 
 // Forcing tables (per side).
@@ -99,8 +98,9 @@ constexpr int STRIP = WAVE - 2 * HALO;  // output columns per wavefront
 constexpr int WAVES_PER_BLOCK = 4;
 
 // Kernel launchers (clf_kernels.hip).
-hipError_t launch_step(int fp32, int order, const GridDesc* grids, const Tile* tiles, int ntiles,
-                       StepState* st, int parity, int count_step, int nblocks, hipStream_t s);
+hipError_t launch_step(int fp32, int order, int gflags, const GridDesc* grids, const Tile* tiles,
+                       int ntiles, StepState* st, int parity, int do_max, int nblocks,
+                       hipStream_t s);
 hipError_t launch_init_state(int fp32, const GridDesc* gd_host, const GridDesc* gd_dev,
                              const double* eta, const double* u, const double* v, int deform,
                              long long N, int parity, hipStream_t s);
@@ -118,9 +118,9 @@ hipError_t launch_get_depth(int fp32, const GridDesc* gd_host, const GridDesc* g
                             long long N, hipStream_t s);
 hipError_t launch_clear_maxwave(int fp32, const GridDesc* gd_host, long long N, hipStream_t s);
 hipError_t launch_sample(int fp32, const GridDesc* gd_dev, const SampleDesc* sd_dev, int nthreads,
-                         StepState* st, int parity, hipStream_t s);
+                         long long n, int parity, hipStream_t s);
 hipError_t launch_forcing(int fp32, const GridDesc* gd_dev, const ForceDesc* fd_dev, int nthreads,
-                          StepState* st, int parity, hipStream_t s);
+                          long long n, int parity, hipStream_t s);
 hipError_t launch_deform_depth(int fp32, const GridDesc* gd_host, const double* eta, long long N,
                                hipStream_t s);
 

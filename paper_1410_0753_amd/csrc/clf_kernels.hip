@@ -28,14 +28,25 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace clf {
 namespace {
 
 constexpr double kG = 9.81;
 
 // ---------------------------------------------------------------------------
-// Cross-lane exchange: value held by lane-1 / lane+1 of the wavefront.
+// Cross-lane exchange: value held by lane-1 / lane+1 of the wavefront, by
+// DPP whole-wave shifts (wave_shr:1 / wave_shl:1).  Lanes without a source
+// (lane 0, lane 63) keep their own value; they lie in the halo.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_prev_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int lane_next_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false);
+}
+
 template <class T>
 __device__ __forceinline__ T from_prev(const T& v) {
   static_assert(sizeof(T) % 4 == 0, "4-byte multiple");
@@ -43,7 +54,7 @@ __device__ __forceinline__ T from_prev(const T& v) {
   U a, b;
   a.v = v;
 #pragma unroll
-  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) b.i[k] = __shfl_up(a.i[k], 1, WAVE);
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) b.i[k] = lane_prev_i(a.i[k]);
   return b.v;
 }
 
@@ -54,8 +65,19 @@ __device__ __forceinline__ T from_next(const T& v) {
   U a, b;
   a.v = v;
 #pragma unroll
-  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) b.i[k] = __shfl_down(a.i[k], 1, WAVE);
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) b.i[k] = lane_next_i(a.i[k]);
   return b.v;
+}
+
+// Loads through the global address space (the field pointers come from a
+// descriptor in memory, so the compiler cannot infer it).
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ void gstore(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -121,8 +143,24 @@ struct P64 {
         }
       }
     }
-    b.c = (b.f & F_WET) ? sqrt(kG * b.H) : 0.0;
     return b;
+  }
+
+  // post-(b) view of a node when no lane of the wavefront can flood
+  static __device__ __forceinline__ B stage_b_copy(const A& c) {
+    B b;
+    b.H = c.H; b.w = c.w; b.t = c.t; b.D = c.D; b.f = c.f; b.src = 0; b.c = 0.0;
+    return b;
+  }
+
+  // a dry node next to a wet one (flags of the neighbours after (a))
+  static __device__ __forceinline__ bool flood_candidate(int f, int fl, int fr) {
+    const int ew = F_EX | F_WET;
+    return (f & F_EX) && !(f & (F_WET | F_FIX)) && (((fl & ew) == ew) || ((fr & ew) == ew));
+  }
+
+  static __device__ __forceinline__ void set_c(B& b) {
+    b.c = (b.f & F_WET) ? sqrt(kG * b.H) : 0.0;
   }
 
   static __device__ __forceinline__ Bx bx(const B& b) {
@@ -173,7 +211,7 @@ struct P64 {
   static __device__ __forceinline__ C stage_cd(const Bx& l, const B& c, const Bx& r, double iL,
                                                double iR, double iS, double tanR, const Par& p) {
     C o;
-    if (c.f & F_FIX) {
+    if ((p.flags & (G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N)) && (c.f & F_FIX)) {
       o.H = c.H; o.w = c.w; o.t = c.t;
       return o;
     }
@@ -240,7 +278,8 @@ struct P64 {
     return x;
   }
 
-  static __device__ __forceinline__ void stage_e(C& o, const Cx& l, const Cx& r, int src) {
+  static __device__ __forceinline__ void stage_e(C& o, const Cx& l, const Cx& r, int src,
+                                                 double /*D*/) {
     if (src == 0) return;
     if (src == 2) {
       double a = l.H, b = r.H;
@@ -266,6 +305,223 @@ struct P64 {
 };
 
 // ---------------------------------------------------------------------------
+// FP32 node stages.  The stored state is the surface eta (field "H" of the
+// views holds eta), so that a node at rest over 4000 m keeps its surface to
+// the last bit.  The update is the algebraically identical perturbation form
+// of eqQ and solver2:
+//   Q_P = [ (l_a + l_b)/2 (w_b - w_a) + g (eta_b - eta_a)
+//           + g (h_b - h_a) (w_a + w_b)/(c_a + c_b) ] / dx,   Q_M: minus sign,
+//   p' - p = -dt/2 (QL + QR) + lambda dt^2 (QR - QL)/(dx_l + dx_r),
+//   u' = u + (dp + dq)/2,  h' = h + d (8c + d)/16g with d = dp - dq,
+// which is zero to the bit for a lake at rest.
+// ---------------------------------------------------------------------------
+struct P32 {
+  typedef float R;
+  static constexpr float kGf = 9.81f;
+  struct A { float H, w, t, D; int f; int pad; };          // H = eta
+  struct B { float H, w, t, D, c, h; int f; int src; };   // h = total height
+  struct Bx { float w, t, D, c, H, h; int f; int pad; };
+  struct C { float H, w, t, h; };                         // eta', u', v', h'
+  struct Cx { float h, w; };
+
+  struct Par {
+    float dt, hdt, dt2, hmin, gn2, inv16g, dwall;
+    int flags;
+  };
+
+  static __device__ __forceinline__ void stage_a(A& a, const Par& p) {
+    if (a.f & F_EX) {
+      if (a.D + a.H > p.hmin) {
+        a.f |= F_WET;
+      } else {
+        a.H = -a.D; a.w = 0.f; a.t = 0.f;
+      }
+    }
+  }
+
+  static __device__ __forceinline__ B stage_b(const A& l, const A& c, const A& r, const Par& p) {
+    B b;
+    b.H = c.H; b.w = c.w; b.t = c.t; b.D = c.D; b.f = c.f; b.src = 0;
+    b.h = c.D + c.H;
+    const bool blocked = (p.flags & G_WALLMODE) && (c.D < p.dwall);
+    if ((c.f & F_EX) && !(c.f & (F_WET | F_FIX)) && !blocked) {
+      bool qL = false, qR = false;
+      float fL = 0.f, fR = 0.f;
+      if ((l.f & (F_EX | F_WET)) == (F_EX | F_WET)) {
+        fL = l.H + c.D;
+        qL = fL > p.hmin;
+      }
+      if ((r.f & (F_EX | F_WET)) == (F_EX | F_WET)) {
+        fR = r.H + c.D;
+        qR = fR > p.hmin;
+      }
+      int s = 0;
+      if (qL && qR) s = (fL > fR) ? -1 : ((fR > fL) ? 1 : 2);
+      else if (qL) s = -1;
+      else if (qR) s = 1;
+      if (s != 0) {
+        b.src = s;
+        b.f |= F_WET | F_FLD;
+        b.h = p.hmin;
+        b.H = p.hmin - c.D;
+        if (s == 2) {
+          b.w = 0.5f * (l.w + r.w);
+          b.t = 0.5f * (l.t + r.t);
+        } else if (s == -1) {
+          b.w = l.w; b.t = l.t;
+        } else {
+          b.w = r.w; b.t = r.t;
+        }
+      }
+    }
+    return b;
+  }
+
+  static __device__ __forceinline__ B stage_b_copy(const A& c) {
+    B b;
+    b.H = c.H; b.w = c.w; b.t = c.t; b.D = c.D; b.f = c.f; b.src = 0; b.c = 0.f;
+    b.h = c.D + c.H;
+    return b;
+  }
+
+  static __device__ __forceinline__ bool flood_candidate(int f, int fl, int fr) {
+    const int ew = F_EX | F_WET;
+    return (f & F_EX) && !(f & (F_WET | F_FIX)) && (((fl & ew) == ew) || ((fr & ew) == ew));
+  }
+
+  static __device__ __forceinline__ void set_c(B& b) {
+    b.c = (b.f & F_WET) ? sqrtf(kGf * b.h) : 0.f;
+  }
+
+  static __device__ __forceinline__ Bx bx(const B& b) {
+    Bx x;
+    x.w = b.w; x.t = b.t; x.D = b.D; x.c = b.c; x.H = b.H; x.h = b.h; x.f = b.f; x.pad = 0;
+    return x;
+  }
+
+  // perturbation-form Q of the P (sg = +1) or M (sg = -1) family across the
+  // interface a|b
+  static __device__ __forceinline__ float qpm(float sg, float wa, float ca, float ea, float Da,
+                                              float wb, float cb, float eb, float Db, float inv) {
+    const float sw = wb + wa, dw = wb - wa, sc = cb + ca;
+    const float de = eb - ea;
+    const float dh = (Db - Da) + de;
+    const float lam2 = sw + sg * sc;
+    const float adv = 0.5f * lam2 * dw;
+    const float grav = kGf * de;
+    const float cross = kGf * dh * (sw / sc);
+    return (adv + grav + sg * cross) * inv;
+  }
+
+  static __device__ __forceinline__ float qt(float wa, float ta, float wb, float tb, float inv) {
+    return (0.5f * (wb + wa) * (tb - ta)) * inv;
+  }
+
+  static __device__ __forceinline__ float incr(const Par& p, float lam, float QL, float QR, float Qc,
+                                               float iS) {
+    const float first = (p.flags & G_SOLVER1) ? -(p.dt * Qc) : -(p.hdt * (QL + QR));
+    return first + ((lam * p.dt2) * (QR - QL)) * iS;
+  }
+
+  static __device__ __forceinline__ C stage_cd(const Bx& l, const B& c, const Bx& r, float iL,
+                                               float iR, float iS, float tanR, const Par& p) {
+    C o;
+    if ((p.flags & (G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N)) && (c.f & F_FIX)) {
+      o.H = c.H; o.w = c.w; o.t = c.t; o.h = c.h;
+      return o;
+    }
+    if (!(c.f & F_WET)) {
+      o.H = -c.D; o.w = 0.f; o.t = 0.f; o.h = 0.f;
+      return o;
+    }
+    float Lw, Lt, LD, Lc, Le, Rw, Rt, RD, Rc, Re;
+    if ((l.f & (F_EX | F_WET)) == (F_EX | F_WET)) {
+      Lw = l.w; Lt = l.t; LD = l.D; Lc = l.c; Le = l.H;
+    } else {
+      Lw = -c.w; Lt = c.t; LD = c.D; Lc = c.c; Le = c.H;   // mirror ghost
+    }
+    if ((r.f & (F_EX | F_WET)) == (F_EX | F_WET)) {
+      Rw = r.w; Rt = r.t; RD = r.D; Rc = r.c; Re = r.H;
+    } else {
+      Rw = -c.w; Rt = c.t; RD = c.D; Rc = c.c; Re = c.H;
+    }
+    const float Cw = c.w, Ct = c.t, CD = c.D, Cc = c.c, Ce = c.H;
+    const float QPL = qpm(1.f, Lw, Lc, Le, LD, Cw, Cc, Ce, CD, iL);
+    const float QPR = qpm(1.f, Cw, Cc, Ce, CD, Rw, Rc, Re, RD, iR);
+    const float QML = qpm(-1.f, Lw, Lc, Le, LD, Cw, Cc, Ce, CD, iL);
+    const float QMR = qpm(-1.f, Cw, Cc, Ce, CD, Rw, Rc, Re, RD, iR);
+    const float QTL = qt(Lw, Lt, Cw, Ct, iL);
+    const float QTR = qt(Cw, Ct, Rw, Rt, iR);
+    float QPc = 0.f, QMc = 0.f, QTc = 0.f;
+    if (p.flags & G_SOLVER1) {
+      QPc = qpm(1.f, Lw, Lc, Le, LD, Rw, Rc, Re, RD, iS);
+      QMc = qpm(-1.f, Lw, Lc, Le, LD, Rw, Rc, Re, RD, iS);
+      QTc = qt(Lw, Lt, Rw, Rt, iS);
+    }
+    float dP = incr(p, Cw + Cc, QPL, QPR, QPc, iS);
+    float dM = incr(p, Cw - Cc, QML, QMR, QMc, iS);
+    const float dT = incr(p, Cw, QTL, QTR, QTc, iS);
+    if (tanR != 0.f) {
+      const float s3 = ((p.dt * Cc) * Cw) * tanR;
+      dP = dP + s3;
+      dM = dM - s3;
+    }
+    float wv = Cw + 0.5f * (dP + dM);
+    const float dd = dP - dM;
+    float hv, ev;
+    if (4.f * Cc + dd < 0.f) {
+      hv = 0.f;
+      ev = -CD;
+    } else {
+      const float dh = (dd * (8.f * Cc + dd)) * p.inv16g;
+      hv = c.h + dh;
+      ev = Ce + dh;
+    }
+    if (p.flags & G_FRICTION) {
+      const float sp = sqrtf(Cw * Cw + Ct * Ct);
+      const float den = c.h * cbrtf(c.h);
+      const float fr = ((p.dt * p.gn2) * sp) / den;
+      wv = wv / (1.f + fr);
+    }
+    o.H = ev; o.w = wv; o.t = Ct + dT; o.h = hv;
+    return o;
+  }
+
+  static __device__ __forceinline__ Cx cx(const C& c) {
+    Cx x;
+    x.h = c.h; x.w = c.w;
+    return x;
+  }
+
+  static __device__ __forceinline__ void stage_e(C& o, const Cx& l, const Cx& r, int src,
+                                                 float D) {
+    if (src == 0) return;
+    float cap;
+    if (src == 2) {
+      const float m = (r.h < l.h) ? r.h : l.h;
+      cap = 0.5f * m;
+    } else {
+      const Cx& s = (src == -1) ? l : r;
+      cap = 0.5f * s.h;
+      if (src == -1) {
+        if (o.w > s.w) o.w = s.w;
+      } else {
+        if (o.w < s.w) o.w = s.w;
+      }
+    }
+    if (o.h > cap) {
+      o.h = cap;
+      o.H = cap - D;
+    }
+  }
+
+  static __device__ __forceinline__ bool wet_out(const C& o, float D, const Par& p) {
+    return D + o.H > p.hmin;
+  }
+  static __device__ __forceinline__ float eta_out(const C& o, float /*D*/) { return o.H; }
+};
+
+// ---------------------------------------------------------------------------
 // The march kernel.
 // ---------------------------------------------------------------------------
 template <class P>
@@ -280,9 +536,6 @@ struct Ctx {
   const R* D;
   R* emax;
   R* smax2;
-  const R* xib;
-  const R* xisb;
-  const R* xfac;
   const R* yib;
   const R* yisb;
   const R* tanR;
@@ -290,7 +543,6 @@ struct Ctx {
   typename P::Par par;
 };
 
-template <class P>
 __device__ __forceinline__ int ring_flag(int gflags, int xc, int r, int nx, int ny) {
   return ((gflags & G_FIX_W) && xc == 0) || ((gflags & G_FIX_E) && xc == nx - 1) ||
                  ((gflags & G_FIX_S) && r == 0) || ((gflags & G_FIX_N) && r == ny - 1)
@@ -298,8 +550,10 @@ __device__ __forceinline__ int ring_flag(int gflags, int xc, int r, int nx, int 
              : 0;
 }
 
-// x-sweep of one row across the wavefront.  In: post-(a) node of this lane
-// along x (w = u, t = v).  Out: post-sweep (H, u, v) (valid on lanes 3..60).
+// x-sweep of one row across the wavefront.  In: this lane's node along x
+// (w = u, t = v), unflagged wet state.  Out: post-sweep (H, u, v), valid on
+// lanes 3..60.  The flooding exchange of step (b) and the limiter exchange
+// of step (e) run only when some lane of the wavefront needs them.
 template <class P>
 __device__ __forceinline__ typename P::C xsweep_row(typename P::A a, typename P::R iL,
                                                     typename P::R iR, typename P::R iS,
@@ -308,82 +562,108 @@ __device__ __forceinline__ typename P::C xsweep_row(typename P::A a, typename P:
   typedef typename P::B B;
   typedef typename P::C C;
   P::stage_a(a, par);
-  A al = from_prev(a);
-  A ar = from_next(a);
-  B b = P::stage_b(al, a, ar, par);
+  const int fl = lane_prev_i(a.f), fr = lane_next_i(a.f);
+  B b;
+  if (__ballot(P::flood_candidate(a.f, fl, fr)) != 0) {
+    A al = from_prev(a);
+    A ar = from_next(a);
+    b = P::stage_b(al, a, ar, par);
+  } else {
+    b = P::stage_b_copy(a);
+  }
+  P::set_c(b);
   typename P::Bx bx = P::bx(b);
   typename P::Bx bl = from_prev(bx);
   typename P::Bx br = from_next(bx);
   C c = P::stage_cd(bl, b, br, iL, iR, iS, (typename P::R)0, par);
-  typename P::Cx cc = P::cx(c);
-  typename P::Cx cl = from_prev(cc);
-  typename P::Cx cr = from_next(cc);
-  if (b.f & F_EX) P::stage_e(c, cl, cr, b.src);
+  if (__ballot(b.src != 0) != 0) {
+    typename P::Cx cc = P::cx(c);
+    typename P::Cx cl = from_prev(cc);
+    typename P::Cx cr = from_next(cc);
+    if (b.f & F_EX) P::stage_e(c, cl, cr, b.src, b.D);
+  }
   return c;
 }
 
-// Per-lane y pipeline: register windows of the stages.
+// Per-lane y pipeline: rotating register windows of the stages.  Row r is
+// pushed in phase K = (r - first) mod 3; slot indices are compile-time so the
+// windows rotate by renaming, not by moves.  After the push of row r:
+//   a[(K+1)%3], a[(K+2)%3], a[K] = post-(a) rows r-2, r-1, r
+//   b[(K+1)%3], b[(K+2)%3], b[K] = post-(b) rows r-3, r-2, r-1
+//   c[(K+1)%3], c[(K+2)%3], c[K] = post-(d) rows r-4, r-3, r-2
 template <class P>
 struct YPipe {
-  typename P::A a0, a1, a2;   // rows r-2, r-1, r  (post-(a))
-  typename P::B b0, b1, b2;   // rows r-3, r-2, r-1 (post-(b))
-  typename P::C c0, c1, c2;   // rows r-4, r-3, r-2 (post-(d))
+  typename P::A a[3];
+  typename P::B b[3];
+  typename P::C c[3];
 
   __device__ __forceinline__ void reset() {
-    a0.f = a1.f = a2.f = 0;
-    b0.f = b1.f = b2.f = 0;
-    b0.src = b1.src = b2.src = 0;
-    a0.H = a1.H = a2.H = 0; a0.w = a1.w = a2.w = 0; a0.t = a1.t = a2.t = 0;
-    a0.D = a1.D = a2.D = 0;
-    b0.H = b1.H = b2.H = 0; b0.w = b1.w = b2.w = 0; b0.t = b1.t = b2.t = 0;
-    b0.D = b1.D = b2.D = 0; b0.c = b1.c = b2.c = 0;
-    c0.H = c1.H = c2.H = 0; c0.w = c1.w = c2.w = 0; c0.t = c1.t = c2.t = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a[k] = typename P::A{};
+      b[k] = typename P::B{};
+      c[k] = typename P::C{};
+    }
   }
 };
 
-// Push row r (y view: w = v, t = u) into the pipeline; returns the final
-// state of row r-3 in `out` and its post-(b) view (flags, depth, flood
-// source) in `ob`.
-template <class P>
-__device__ __forceinline__ void ypipe_push(YPipe<P>& y, typename P::A a, int r,
+// Push row r (y view: w = v, t = u) in phase K; returns the final state of
+// row r-3 in `out` and its post-(b) view (flags, depth, flood source) in `ob`.
+template <class P, int K>
+__device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_in, int r,
                                            const Ctx<P>& cx, typename P::C& out,
                                            typename P::B& ob) {
   typedef typename P::R R;
-  P::stage_a(a, cx.par);
-  y.a0 = y.a1; y.a1 = y.a2; y.a2 = a;
+  constexpr int K1 = (K + 1) % 3, K2 = (K + 2) % 3;
+  y.a[K] = a_in;
+  P::stage_a(y.a[K], cx.par);
   // (b) on row r-1
-  typename P::B bn = P::stage_b(y.a0, y.a1, y.a2, cx.par);
-  y.b0 = y.b1; y.b1 = y.b2; y.b2 = bn;
-  // (c)+(d) on row r-2 (the centre of the b window)
+  y.b[K] = P::stage_b(y.a[K1], y.a[K2], y.a[K], cx.par);
+  P::set_c(y.b[K]);
+  // (c)+(d) on row r-2
   const int rc = r - 2;
   R iL = 1, iR = 1, iS = 1, tr = 0;
   if (rc >= 0 && rc < cx.ny) {
-    iL = cx.yib[rc];
-    iR = cx.yib[rc + 1];
-    iS = cx.yisb[rc];
-    if (cx.gflags & G_SPHSRC) tr = cx.tanR[rc];
+    iL = gload(cx.yib + rc);
+    iR = gload(cx.yib + rc + 1);
+    iS = gload(cx.yisb + rc);
+    if (cx.par.flags & G_SPHSRC) tr = gload(cx.tanR + rc);
   }
-  typename P::C cn = P::stage_cd(P::bx(y.b0), y.b1, P::bx(y.b2), iL, iR, iS, tr, cx.par);
-  y.c0 = y.c1; y.c1 = y.c2; y.c2 = cn;
-  // (e) on row r-3: centre of the c window; its (b) view is now b0
-  out = y.c1;
-  ob = y.b0;
-  if (ob.f & F_EX) P::stage_e(out, P::cx(y.c0), P::cx(y.c2), ob.src);
+  y.c[K] = P::stage_cd(P::bx(y.b[K1]), y.b[K2], P::bx(y.b[K]), iL, iR, iS, tr, cx.par);
+  // (e) on row r-3
+  out = y.c[K2];
+  ob = y.b[K1];
+  if (ob.src != 0) P::stage_e(out, P::cx(y.c[K1]), P::cx(y.c[K]), ob.src, ob.D);
 }
 
-template <class P, int ORDER>
+// FL: the grid flags this instantiation honours (others are compiled out).
+constexpr int FL_FAST = G_SPHSRC;
+constexpr int FL_ALL = G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N | G_WALLMODE | G_SOLVER1 |
+                       G_SPHSRC | G_FRICTION;
+
+#ifndef CLF_STEP_WAVES_PER_EU
+#define CLF_STEP_WAVES_PER_EU 2
+#endif
+
+template <class P, int ORDER, int FL>
 __global__ void __launch_bounds__(WAVE * WAVES_PER_BLOCK)
+__attribute__((amdgpu_waves_per_eu(CLF_STEP_WAVES_PER_EU)))
 step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, int ntiles,
-            StepState* st, int parity, int count_step) {
+            StepState* st, int parity, int do_max) {
   typedef typename P::R R;
   typedef typename P::A A;
   typedef typename P::C C;
   const int lane = threadIdx.x & (WAVE - 1);
-  const int wave = threadIdx.x / WAVE;
+  // the wave index is uniform across the wavefront: say so, so that the
+  // tile, the row counter and the row metrics live in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int tid = blockIdx.x * WAVES_PER_BLOCK + wave;
-  const long long n0 = st->n;
   if (tid < ntiles) {
-    const Tile tl = tiles[tid];
+    Tile tl = tiles[tid];
+    tl.grid = __builtin_amdgcn_readfirstlane(tl.grid);
+    tl.x0 = __builtin_amdgcn_readfirstlane(tl.x0);
+    tl.y0 = __builtin_amdgcn_readfirstlane(tl.y0);
+    tl.rows = __builtin_amdgcn_readfirstlane(tl.rows);
     const GridDesc& g = grids[tl.grid];
     Ctx<P> cx;
     cx.H = (const R*)g.H[parity];
@@ -395,15 +675,12 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
     cx.D = (const R*)g.D;
     cx.emax = (R*)g.emax;
     cx.smax2 = (R*)g.smax2;
-    cx.xib = (const R*)g.xib;
-    cx.xisb = (const R*)g.xisb;
-    cx.xfac = (const R*)g.xfac;
     cx.yib = (const R*)g.yib;
     cx.yisb = (const R*)g.yisb;
     cx.tanR = (const R*)g.tanR;
     cx.nx = g.nx;
     cx.ny = g.ny;
-    cx.gflags = g.flags;
+    cx.gflags = g.flags & FL;
     cx.par.dt = (R)g.dt;
     cx.par.hdt = (R)g.hdt;
     cx.par.dt2 = (R)g.dt2;
@@ -411,8 +688,9 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
     cx.par.gn2 = (R)g.gn2;
     cx.par.inv16g = (R)g.inv16g;
     cx.par.dwall = (R)g.dwall;
-    cx.par.flags = g.flags;
-    const bool do_max = count_step && ((n0 + 1) % g.maxout == 0);
+    cx.par.flags = g.flags & FL;
+    const R* xfac = (const R*)g.xfac;
+    constexpr bool kRing = (FL & (G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N)) != 0;
 
     const int nx = cx.nx, ny = cx.ny;
     const int xc = tl.x0 - HALO + lane;
@@ -421,9 +699,9 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
     // per-lane x metrics (constant along the march)
     R xiL = 1, xiR = 1, xiS = 1;
     if (col_in) {
-      xiL = cx.xib[xc];
-      xiR = cx.xib[xc + 1];
-      xiS = cx.xisb[xc];
+      xiL = gload((const R*)g.xib + xc);
+      xiR = gload((const R*)g.xib + xc + 1);
+      xiS = gload((const R*)g.xisb + xc);
     }
     int bad = 0;
 
@@ -432,100 +710,115 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
       a.H = 0; a.w = 0; a.t = 0; a.D = 0;
       if (r >= 0 && r < ny && col_in) {
         const long long k = (long long)r * nx + xc;
-        a.H = cx.H[k];
-        a.D = cx.D[k];
-        a.w = cx.U[k];   // x view: w = u, t = v
-        a.t = cx.V[k];
-        a.f = F_EX | ring_flag<P>(cx.gflags, xc, r, nx, ny);
+        a.H = gload(cx.H + k);
+        a.D = gload(cx.D + k);
+        a.w = gload(cx.U + k);   // x view: w = u, t = v
+        a.t = gload(cx.V + k);
+        a.f = F_EX;
+        if (kRing) a.f |= ring_flag(cx.gflags, xc, r, nx, ny);
       }
     };
-    auto store = [&](int r, const C& o, R D) {
+    // maxwave values of an output row, read one march row ahead of use
+    struct MW { R e, s2; };
+    auto load_mw = [&](int r, MW& m) {
+      m.e = 0; m.s2 = 0;
+      if (do_max && out_lane && r >= 0 && r < ny) {
+        const long long k = (long long)r * nx + xc;
+        m.e = gload(cx.emax + k);
+        m.s2 = gload(cx.smax2 + k);
+      }
+    };
+    auto store = [&](int r, const C& o, R D, const MW& m) {
       // o in x view: H, w = u, t = v
       if (!out_lane || r < 0 || r >= ny) return;
       const long long k = (long long)r * nx + xc;
-      cx.Ho[k] = o.H;
-      cx.Uo[k] = o.w;
-      cx.Vo[k] = o.t;
+      gstore(cx.Ho + k, o.H);
+      gstore(cx.Uo + k, o.w);
+      gstore(cx.Vo + k, o.t);
       if (!(isfinite(o.H) && isfinite(o.w) && isfinite(o.t))) bad = 1;
       if (do_max && P::wet_out(o, D, cx.par)) {
         R e = P::eta_out(o, D);
-        if (e > cx.emax[k]) cx.emax[k] = e;
+        if (e > m.e) gstore(cx.emax + k, e);
         R s2 = o.w * o.w + o.t * o.t;
-        if (s2 > cx.smax2[k]) cx.smax2[k] = s2;
+        if (s2 > m.s2) gstore(cx.smax2 + k, s2);
       }
     };
 
     if (ORDER == ORD_X) {
+      A nxt;
+      MW mnxt;
+      load_row(tl.y0, nxt);
+      load_mw(tl.y0, mnxt);
       for (int r = tl.y0; r < tl.y0 + tl.rows; ++r) {
-        A a;
-        load_row(r, a);
-        R f = cx.xfac[r];
+        A a = nxt;
+        MW m = mnxt;
+        load_row(r + 1, nxt);
+        load_mw(r + 1, mnxt);
+        R f = gload(xfac + r);
         C o = xsweep_row<P>(a, f * xiL, f * xiR, f * xiS, cx.par);
-        store(r, o, a.D);
+        store(r, o, a.D, m);
       }
-    } else if (ORDER == ORD_Y || ORDER == ORD_XY) {
+    } else {
       YPipe<P> yp;
       yp.reset();
-      for (int r = tl.y0 - HALO; r < tl.y0 + tl.rows + HALO; ++r) {
-        A a;
-        load_row(r, a);
-        if (ORDER == ORD_XY && r >= 0 && r < ny) {
-          R f = cx.xfac[r];
-          C o = xsweep_row<P>(a, f * xiL, f * xiR, f * xiS, cx.par);
-          a.H = o.H; a.w = o.w; a.t = o.t;
-          a.f &= (F_EX | F_FIX);
+      A pf[3];
+      MW pm[3];
+      const int r_first = tl.y0 - HALO, r_end = tl.y0 + tl.rows + HALO;
+      load_row(r_first, pf[0]);
+      load_mw(r_first - HALO, pm[0]);
+      // one march row in phase K: consume pf[K] (row r) and pm[K] (maxwave of
+      // the output row r-3); prefetch row r+1 and the maxwave of row r-2
+      auto body = [&](auto phase, int r) {
+        constexpr int K = decltype(phase)::value;
+        A a = pf[K];
+        MW m = pm[K];
+        load_row(r + 1, pf[(K + 1) % 3]);
+        load_mw(r + 1 - HALO, pm[(K + 1) % 3]);
+        if (ORDER == ORD_YX) {
+          A ay = a;
+          ay.w = a.t;
+          ay.t = a.w;
+          C oy;
+          typename P::B ob;
+          ypipe_push<P, K>(yp, ay, r, cx, oy, ob);
+          const int ro = r - HALO;
+          if (ro >= tl.y0 && ro < ny) {
+            A ax;
+            ax.H = oy.H; ax.w = oy.t; ax.t = oy.w;
+            ax.f = ob.f & (F_EX | F_FIX);
+            ax.D = ob.D;
+            R f = gload(xfac + ro);
+            C o = xsweep_row<P>(ax, f * xiL, f * xiR, f * xiS, cx.par);
+            store(ro, o, ax.D, m);
+          }
+        } else {
+          if (ORDER == ORD_XY && r >= 0 && r < ny) {
+            R f = gload(xfac + r);
+            C o = xsweep_row<P>(a, f * xiL, f * xiR, f * xiS, cx.par);
+            a.H = o.H; a.w = o.w; a.t = o.t;
+            a.f &= (F_EX | F_FIX);
+          }
+          A ay = a;   // y view: w = v, t = u
+          ay.w = a.t;
+          ay.t = a.w;
+          C oy;
+          typename P::B ob;
+          ypipe_push<P, K>(yp, ay, r, cx, oy, ob);
+          const int ro = r - HALO;
+          if (ro >= tl.y0) {
+            C o;
+            o.H = oy.H; o.w = oy.t; o.t = oy.w;   // back to x view
+            store(ro, o, ob.D, m);
+          }
         }
-        // y view: w = v, t = u
-        A ay = a;
-        ay.w = a.t;
-        ay.t = a.w;
-        C oy;
-        typename P::B ob;
-        ypipe_push<P>(yp, ay, r, cx, oy, ob);
-        const int ro = r - HALO;
-        if (ro >= tl.y0) {
-          C o;
-          o.H = oy.H; o.w = oy.t; o.t = oy.w;   // back to x view
-          store(ro, o, ob.D);
-        }
-      }
-    } else {  // ORD_YX: y pipeline on the loaded rows, then the x-sweep of its output row
-      YPipe<P> yp;
-      yp.reset();
-      for (int r = tl.y0 - HALO; r < tl.y0 + tl.rows + HALO; ++r) {
-        A a;
-        load_row(r, a);
-        A ay = a;
-        ay.w = a.t;
-        ay.t = a.w;
-        C oy;
-        typename P::B ob;
-        ypipe_push<P>(yp, ay, r, cx, oy, ob);
-        const int ro = r - HALO;
-        if (ro >= tl.y0 && ro < ny) {
-          A ax;
-          ax.H = oy.H; ax.w = oy.t; ax.t = oy.w;
-          ax.f = ob.f & (F_EX | F_FIX);
-          ax.D = ob.D;
-          R f = cx.xfac[ro];
-          C o = xsweep_row<P>(ax, f * xiL, f * xiR, f * xiS, cx.par);
-          store(ro, o, ax.D);
-        }
+      };
+      for (int r = r_first; r < r_end; r += 3) {
+        body(std::integral_constant<int, 0>(), r);
+        if (r + 1 < r_end) body(std::integral_constant<int, 1>(), r + 1);
+        if (r + 2 < r_end) body(std::integral_constant<int, 2>(), r + 2);
       }
     }
     if (bad) st->bad = 1;
-  }
-  // step counter: the last wave to finish advances n (every wave has read
-  // n0 before it arrives here)
-  if (count_step && lane == 0) {
-    __threadfence();
-    const unsigned total = gridDim.x * WAVES_PER_BLOCK;
-    unsigned prev = atomicAdd(&st->done, 1u);
-    if (prev == total - 1) {
-      st->done = 0;
-      st->n = n0 + 1;
-      __threadfence();
-    }
   }
 }
 
@@ -655,9 +948,8 @@ __global__ void get_depth_kernel(GridDesc g, double* d, long long N) {
 
 // Gauge and enclosed-grid records at the level n reached by the last step.
 template <class R>
-__global__ void sample_kernel(const GridDesc* grids, const SampleDesc* sd, StepState* st,
+__global__ void sample_kernel(const GridDesc* grids, const SampleDesc* sd, long long n,
                               int parity) {
-  const long long n = st->n;
   const SampleDesc s = *sd;
   const GridDesc& g = grids[s.grid];
   const R* H = (const R*)g.H[parity];
@@ -665,8 +957,8 @@ __global__ void sample_kernel(const GridDesc* grids, const SampleDesc* sd, StepS
   const R* V = (const R*)g.V[parity];
   const R* D = (const R*)g.D;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s.ngauge > 0 && n % s.gout == 0 && n >= st->g_first && i < s.ngauge) {
-    const long long slot = (n - st->g_first) / s.gout;
+  if (s.ngauge > 0 && n % s.gout == 0 && n >= s.g_first && i < s.ngauge) {
+    const long long slot = (n - s.g_first) / s.gout;
     if (slot < s.gcap) {
       const int k = s.gidx[i];
       R e;
@@ -677,8 +969,8 @@ __global__ void sample_kernel(const GridDesc* grids, const SampleDesc* sd, StepS
       o[2] = w ? (double)V[k] : 0.0;
     }
   }
-  if (s.npts > 0 && n % s.bndout == 0 && n >= st->s_first && i < s.npts) {
-    const long long slot = (n - st->s_first) / s.bndout;
+  if (s.npts > 0 && n % s.bndout == 0 && n >= s.s_first && i < s.npts) {
+    const long long slot = (n - s.s_first) / s.bndout;
     if (slot < s.scap) {
       double ws = 0.0, au = 0.0, av = 0.0, ae = 0.0;
       for (int c = 0; c < 4; ++c) {
@@ -726,11 +1018,11 @@ __device__ __forceinline__ double interp_series(const double* tt, int nt, const 
 }
 
 template <class R>
-__global__ void forcing_kernel(const GridDesc* grids, const ForceDesc* fd, StepState* st,
+__global__ void forcing_kernel(const GridDesc* grids, const ForceDesc* fd, long long n,
                                int parity) {
   const ForceDesc f = *fd;
   const GridDesc& g = grids[f.grid];
-  const double t = (double)st->n * g.dt;
+  const double t = (double)n * g.dt;
   R* H = (R*)g.H[parity];
   R* U = (R*)g.U[parity];
   R* V = (R*)g.V[parity];
@@ -776,27 +1068,45 @@ inline int nblk(long long N, int bs) { return (int)((N + bs - 1) / bs); }
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-hipError_t launch_step(int fp32, int order, const GridDesc* grids, const Tile* tiles, int ntiles,
-                       StepState* st, int parity, int count_step, int nblocks, hipStream_t s) {
-  dim3 grid(nblocks), block(WAVE * WAVES_PER_BLOCK);
-  (void)fp32;
+template <class P, int FL>
+static void launch_order(int order, dim3 grid, dim3 block, hipStream_t s, const GridDesc* grids,
+                         const Tile* tiles, int ntiles, StepState* st, int parity,
+                         int do_max) {
   switch (order) {
     case ORD_XY:
-      hipLaunchKernelGGL((step_kernel<P64, ORD_XY>), grid, block, 0, s, grids, tiles, ntiles, st,
-                         parity, count_step);
+      hipLaunchKernelGGL((step_kernel<P, ORD_XY, FL>), grid, block, 0, s, grids, tiles, ntiles,
+                         st, parity, do_max);
       break;
     case ORD_YX:
-      hipLaunchKernelGGL((step_kernel<P64, ORD_YX>), grid, block, 0, s, grids, tiles, ntiles, st,
-                         parity, count_step);
+      hipLaunchKernelGGL((step_kernel<P, ORD_YX, FL>), grid, block, 0, s, grids, tiles, ntiles,
+                         st, parity, do_max);
       break;
     case ORD_X:
-      hipLaunchKernelGGL((step_kernel<P64, ORD_X>), grid, block, 0, s, grids, tiles, ntiles, st,
-                         parity, count_step);
+      hipLaunchKernelGGL((step_kernel<P, ORD_X, FL>), grid, block, 0, s, grids, tiles, ntiles,
+                         st, parity, do_max);
       break;
     default:
-      hipLaunchKernelGGL((step_kernel<P64, ORD_Y>), grid, block, 0, s, grids, tiles, ntiles, st,
-                         parity, count_step);
+      hipLaunchKernelGGL((step_kernel<P, ORD_Y, FL>), grid, block, 0, s, grids, tiles, ntiles,
+                         st, parity, do_max);
       break;
+  }
+}
+
+hipError_t launch_step(int fp32, int order, int gflags, const GridDesc* grids, const Tile* tiles,
+                       int ntiles, StepState* st, int parity, int do_max, int nblocks,
+                       hipStream_t s) {
+  dim3 grid(nblocks), block(WAVE * WAVES_PER_BLOCK);
+  const bool fast = (gflags & ~FL_FAST) == 0;
+  if (fp32) {
+    if (fast)
+      launch_order<P32, FL_FAST>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+    else
+      launch_order<P32, FL_ALL>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+  } else {
+    if (fast)
+      launch_order<P64, FL_FAST>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+    else
+      launch_order<P64, FL_ALL>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
   }
   return hipGetLastError();
 }
@@ -848,13 +1158,13 @@ hipError_t launch_clear_maxwave(int fp32, const GridDesc* gh, long long N, hipSt
 }
 
 hipError_t launch_sample(int fp32, const GridDesc* gd, const SampleDesc* sd, int nthreads,
-                         StepState* st, int parity, hipStream_t s) {
-  CLF_SMALL_LAUNCH(sample_kernel, (long long)nthreads, gd, sd, st, parity);
+                         long long n, int parity, hipStream_t s) {
+  CLF_SMALL_LAUNCH(sample_kernel, (long long)nthreads, gd, sd, n, parity);
 }
 
 hipError_t launch_forcing(int fp32, const GridDesc* gd, const ForceDesc* fd, int nthreads,
-                          StepState* st, int parity, hipStream_t s) {
-  CLF_SMALL_LAUNCH(forcing_kernel, (long long)nthreads, gd, fd, st, parity);
+                          long long n, int parity, hipStream_t s) {
+  CLF_SMALL_LAUNCH(forcing_kernel, (long long)nthreads, gd, fd, n, parity);
 }
 
 }  // namespace clf

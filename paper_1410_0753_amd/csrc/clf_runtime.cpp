@@ -16,15 +16,19 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 using namespace clf;
 
 namespace {
 
-const bool kHaveFp32Kernels = false;
+const bool kHaveFp32Kernels = true;
 const double kGrav = 9.81;
 const double kPiD = 3.14159265358979323846;
 
@@ -249,7 +253,8 @@ int build_tiles(clf_ctx* c, int seg) {
       tl.rows = std::min(seg, c->ny - q * seg);
       t.push_back(tl);
     }
-  if ((int)t.size() > c->L.ntiles_max) return fail(c, CLF_EINVAL, "tile list overflow");
+  if ((int)t.size() > c->L.ntiles_max)
+    return fail(c, CLF_EINVAL, "segment %d too short (minimum %d rows)", seg, kMinSeg);
   HIPCHK(c, hipMemcpyAsync(c->tiles_dev, t.data(), t.size() * sizeof(Tile),
                            hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -268,6 +273,70 @@ int default_segment(int nx, int ny) {
   return seg;
 }
 
+// Autotuner: time the step kernel on this grid for candidate segment
+// lengths (rows per wavefront tile) from the lake at rest, keep the fastest.
+// Results are cached per (nx, ny, precision, flags) for the process.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tune_cache;
+
+int autotune_segment(clf_ctx* c, int* best_seg) {
+  const auto key = std::make_tuple(c->nx, c->ny, c->fp32, c->gd.flags);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      *best_seg = it->second;
+      return CLF_OK;
+    }
+  }
+  const int cands[] = {16, 24, 32, 48, 64, 96, 128, 192, 256};
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  float best = 1e30f;
+  int bseg = default_segment(c->nx, c->ny);
+  const int order = c->ny == 1 ? ORD_X : (c->nx == 1 ? ORD_Y : ORD_XY);
+  // two rounds over the candidates (the first also warms the clocks); keep
+  // each candidate's best time
+  std::vector<float> tbest(sizeof(cands) / sizeof(cands[0]), 1e30f);
+  for (int round = 0; round < 2; ++round)
+    for (size_t ci = 0; ci < tbest.size(); ++ci) {
+      const int seg = cands[ci];
+      if (seg > 2 * c->ny && ci > 0) break;
+      int rc = build_tiles(c, seg);
+      if (rc) return rc;
+      const int reps = 10;
+      for (int k = 0; k < 3 + reps; ++k) {
+        if (k == 3) HIPCHK(c, hipEventRecord(e0, c->stream));
+        HIPCHK(c, launch_step(c->fp32, order, c->gd.flags, c->gd_dev, c->tiles_dev, c->ntiles,
+                              c->st_dev, c->cur, 1, c->nblocks, c->stream));
+        c->cur ^= 1;
+      }
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      HIPCHK(c, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      tbest[ci] = std::min(tbest[ci], ms);
+    }
+  if (std::getenv("CLF_VERBOSE"))
+    for (size_t ci = 0; ci < tbest.size(); ++ci)
+      std::fprintf(stderr, "clf autotune %dx%d segment %d: %.4f ms / 10 steps\n", c->nx, c->ny,
+                   cands[ci], tbest[ci]);
+  for (size_t ci = 0; ci < tbest.size(); ++ci)
+    if (tbest[ci] < best) {
+      best = tbest[ci];
+      bseg = cands[ci];
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = bseg;
+  }
+  *best_seg = bseg;
+  return CLF_OK;
+}
+
 int check_ready(clf_ctx* c) {
   if (!c) return CLF_EINVAL;
   if (!c->have_state) return fail(c, CLF_ESTATE, "no state: call clf_set_initial first");
@@ -284,17 +353,14 @@ int sync_and_check(clf_ctx* c) {
 
 int push_state(clf_ctx* c) {
   StepState st{};
-  st.n = c->n;
-  st.done = 0;
-  st.bad = 0;
-  st.g_first = c->g_first;
-  st.s_first = c->s_first;
   HIPCHK(c, hipMemcpyAsync(c->st_dev, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return CLF_OK;
 }
 
 int push_sampling(clf_ctx* c) {
+  c->sd.g_first = c->g_first;
+  c->sd.s_first = c->s_first;
   c->sd.ngauge = c->ngauge;
   c->sd.npts = c->npts;
   c->sd.rec_len = c->rec_len;
@@ -344,6 +410,8 @@ void clf_default_params(clf_params* p) {
   p->max_enclosed_points = 4 * 2 * (400 + 400);
   p->series_capacity = 64;
   p->forcing_capacity = 0;
+  p->segment = 0;
+  p->autotune = 0;
 }
 
 static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c) {
@@ -381,6 +449,7 @@ static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c) {
       p->max_enclosed_points < 0 || p->series_capacity < 0 || p->forcing_capacity < 0)
     return fail(c, CLF_EINVAL, "negative capacity");
   if (p->earth_radius <= 0.0) return fail(c, CLF_EINVAL, "earth_radius must be > 0");
+  if (p->segment < 0 || p->segment > 4096) return fail(c, CLF_EINVAL, "segment out of range");
   return CLF_OK;
 }
 
@@ -553,11 +622,17 @@ int clf_init(clf_ctx** out, const clf_grid* g, const double* depth, double dt,
     hipError_t e2 = hipMemcpyAsync(c->fd_dev, &c->fd, sizeof c->fd, hipMemcpyHostToDevice, s);
     if (e2 != hipSuccess) r2 = fail(c, CLF_EHIP, "forcing table upload failed");
   }
-  if (r2 == CLF_OK) r2 = build_tiles(c, default_segment(c->nx, c->ny));
+  int seg = p->segment > 0 ? p->segment : default_segment(c->nx, c->ny);
+  if (r2 == CLF_OK) r2 = build_tiles(c, seg);
   if (r2 == CLF_OK) {
     // lake at rest: h = max(d, 0), dry at or below h_min
     c->have_state = true;
     r2 = clf_set_initial(c, nullptr, nullptr, nullptr, 0);
+  }
+  if (r2 == CLF_OK && p->autotune && p->segment <= 0) {
+    r2 = autotune_segment(c, &seg);
+    if (r2 == CLF_OK) r2 = build_tiles(c, seg);
+    if (r2 == CLF_OK) r2 = clf_set_initial(c, nullptr, nullptr, nullptr, 0);
   }
   if (r2 != CLF_OK) {
     g_init_error = c->err;
@@ -581,7 +656,8 @@ int clf_set_initial(clf_ctx* c, const double* eta, const double* u, const double
   c->rec0 = false;
   c->g_first = 0;
   c->s_first = 0;
-  return push_state(c);
+  int rc = push_state(c);
+  return rc ? rc : push_sampling(c);
 }
 
 int clf_set_raw_state(clf_ctx* c, const double* h, const double* u, const double* v, int64_t n) {
@@ -596,7 +672,8 @@ int clf_set_raw_state(clf_ctx* c, const double* h, const double* u, const double
   c->rec0 = n > 0;  // the record of level n was taken by the run that reached it
   c->g_first = next_level(c->rec0 ? n + 1 : n, c->p.gout);
   c->s_first = next_level(c->rec0 ? n + 1 : n, c->p.bndout);
-  return push_state(c);
+  int rc = push_state(c);
+  return rc ? rc : push_sampling(c);
 }
 
 int clf_get_raw_state(clf_ctx* c, double* h, double* u, double* v) {
@@ -652,13 +729,7 @@ int clf_set_gauges(clf_ctx* c, int n, const int32_t* ix, const int32_t* iy) {
   c->ngauge = n;
   // records restart at the current level (or at 0 before the first step)
   c->g_first = c->rec0 ? next_level(c->n + 1, c->p.gout) : next_level(c->n, c->p.gout);
-  int rc = push_sampling(c);
-  if (rc) return rc;
-  StepState st{};
-  HIPCHK(c, hipMemcpy(&st, c->st_dev, sizeof st, hipMemcpyDeviceToHost));
-  st.g_first = c->g_first;
-  HIPCHK(c, hipMemcpy(c->st_dev, &st, sizeof st, hipMemcpyHostToDevice));
-  return CLF_OK;
+  return push_sampling(c);
 }
 
 int clf_add_enclosed_grid(clf_ctx* c, int nx, int ny, const double* x, const double* y, int* id) {
@@ -743,18 +814,16 @@ int clf_add_enclosed_grid(clf_ctx* c, int nx, int ny, const double* x, const dou
   c->s_first = c->rec0 ? next_level(c->n + 1, c->p.bndout) : next_level(c->n, c->p.bndout);
   int rc = push_sampling(c);
   if (rc) return rc;
-  StepState st{};
-  HIPCHK(c, hipMemcpy(&st, c->st_dev, sizeof st, hipMemcpyDeviceToHost));
-  st.s_first = c->s_first;
-  HIPCHK(c, hipMemcpy(c->st_dev, &st, sizeof st, hipMemcpyHostToDevice));
   if (id) *id = (int)c->enc.size() - 1;
   return CLF_OK;
 }
 
 static int launch_sampling(clf_ctx* c) {
-  if (c->ngauge == 0 && c->npts == 0) return CLF_OK;
-  const int nthr = std::max(c->ngauge, c->npts);
-  HIPCHK(c, launch_sample(c->fp32, c->gd_dev, c->sd_dev, nthr, c->st_dev, c->cur, c->stream));
+  const bool g = c->ngauge > 0 && c->n % c->p.gout == 0 && c->n >= c->g_first;
+  const bool e = c->npts > 0 && c->n % c->p.bndout == 0 && c->n >= c->s_first;
+  if (!g && !e) return CLF_OK;
+  const int nthr = std::max(g ? c->ngauge : 0, e ? c->npts : 0);
+  HIPCHK(c, launch_sample(c->fp32, c->gd_dev, c->sd_dev, nthr, c->n, c->cur, c->stream));
   return CLF_OK;
 }
 
@@ -793,10 +862,11 @@ int clf_step(clf_ctx* c, int nsteps) {
   }
   for (int k = 0; k < nsteps; ++k) {
     if (c->forcing)
-      HIPCHK(c, launch_forcing(c->fp32, c->gd_dev, c->fd_dev, std::max(c->nx, c->ny), c->st_dev,
+      HIPCHK(c, launch_forcing(c->fp32, c->gd_dev, c->fd_dev, std::max(c->nx, c->ny), c->n,
                                c->cur, c->stream));
-    HIPCHK(c, launch_step(c->fp32, step_order(c), c->gd_dev, c->tiles_dev, c->ntiles, c->st_dev,
-                          c->cur, 1, c->nblocks, c->stream));
+    const int do_max = ((c->n + 1) % c->p.maxout) == 0;
+    HIPCHK(c, launch_step(c->fp32, step_order(c), c->gd.flags, c->gd_dev, c->tiles_dev, c->ntiles,
+                          c->st_dev, c->cur, do_max, c->nblocks, c->stream));
     c->cur ^= 1;
     c->n += 1;
     rc = launch_sampling(c);
@@ -811,7 +881,7 @@ int clf_sweep(clf_ctx* c, int axis) {
   if (axis != 0 && axis != 1) return fail(c, CLF_EINVAL, "axis must be 0 or 1");
   if ((axis == 0 && c->nx == 1) || (axis == 1 && c->ny == 1))
     return fail(c, CLF_EINVAL, "no sweep along a dimension of length 1");
-  HIPCHK(c, launch_step(c->fp32, axis == 0 ? ORD_X : ORD_Y, c->gd_dev, c->tiles_dev, c->ntiles,
+  HIPCHK(c, launch_step(c->fp32, axis == 0 ? ORD_X : ORD_Y, c->gd.flags, c->gd_dev, c->tiles_dev, c->ntiles,
                         c->st_dev, c->cur, 0, c->nblocks, c->stream));
   c->cur ^= 1;
   return CLF_OK;
@@ -896,12 +966,7 @@ int clf_clear_records(clf_ctx* c) {
   c->g_first = next_level(from, c->p.gout);
   c->s_first = next_level(from, c->p.bndout);
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  StepState st{};
-  HIPCHK(c, hipMemcpy(&st, c->st_dev, sizeof st, hipMemcpyDeviceToHost));
-  st.g_first = c->g_first;
-  st.s_first = c->s_first;
-  HIPCHK(c, hipMemcpy(c->st_dev, &st, sizeof st, hipMemcpyHostToDevice));
-  return CLF_OK;
+  return push_sampling(c);
 }
 
 int clf_sync(clf_ctx* c) {

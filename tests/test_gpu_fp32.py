@@ -1,0 +1,113 @@
+"""FP32 path: stores eta and advances perturbations.  No bitwise pin exists
+against the FP64 oracle; the error is measured and bounded: max and RMS eta
+error relative to the wave amplitude, and the fraction of nodes whose wet
+flag differs.  Exact properties of the perturbation form are checked to the
+bit: rest over deep water with land, and mirror symmetry."""
+import numpy as np
+import pytest
+
+from paper_1410_0753_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def clf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1410_0753_amd import clf as m
+    m.load()
+    return m
+
+
+def fp32_report(g, o):
+    eg, ug, vg, wg = (t.cpu().numpy() for t in g.state())
+    eo, uo, vo, wo = o.state()
+    amp = max(np.abs(eo).max(), 1e-12)
+    err = np.abs(eg - eo)
+    return {"max_eta_err": float(err.max() / amp), "rms_eta_err": float(np.sqrt((err ** 2).mean()) / amp),
+            "mask_flip": float((wg.astype(bool) != wo.astype(bool)).mean()),
+            "max_u_err": float(np.abs(ug - uo).max() / max(np.abs(uo).max(), 1e-12))}
+
+
+@pytest.mark.parametrize("label,gen,steps", [
+    ("c1-120x90", lambda: synth.config1(nx=120, ny=90, steps=10), 100),
+    ("random-land-130x75", lambda: synth.random_small(1, 130, 75, land=True), 60),
+    ("c2-spherical-scale12", lambda: synth.config2(steps=10, scale=12), 60),
+], ids=["c1", "random-land", "spherical"])
+def test_fp32_error_vs_oracle(clf, oracle_mod, label, gen, steps):
+    case = gen()
+    g = clf.Solver.from_case(case, precision=clf.FP32)
+    o = oracle_mod.Oracle.from_case(case)
+    for obj in (g, o):
+        obj.set_initial(2.0 * case.eta0, case.u0, case.v0)
+        obj.step(steps)
+    r = fp32_report(g, o)
+    print(label, r)
+    assert r["max_eta_err"] <= 2e-3
+    assert r["rms_eta_err"] <= 2e-4
+    assert r["mask_flip"] <= 2e-3
+
+
+def test_fp32_lake_at_rest_exact(clf):
+    # 4000 m deep basin with land and a shelf: the surface stays exactly 0
+    case = synth.config2(steps=10, scale=12)
+    g = clf.Solver.from_case(case, precision=clf.FP32)
+    g.set_initial(None)
+    w0 = g.state()[3].cpu().numpy()
+    g.step(500)
+    e, u, v, w = (t.cpu().numpy() for t in g.state())
+    assert np.array_equal(w, w0)
+    assert np.abs(e).max() == 0.0 and np.abs(u).max() == 0.0 and np.abs(v).max() == 0.0
+
+
+def test_fp32_mirror_symmetry_bitwise(clf):
+    c = synth.random_small(11, 96, 40, land=True)
+    x = np.arange(96) * 100.0
+    y = np.arange(40) * 100.0
+    dt = synth.cfl_dt(0, x, y, np.maximum(c.depth, 1.0), cfl=0.5)
+    a = clf.Solver(x, y, c.depth, dt, precision=clf.FP32)
+    b = clf.Solver(x, y, c.depth[:, ::-1].copy(), dt, precision=clf.FP32)
+    a.set_initial(c.eta0, c.u0, c.v0)
+    b.set_initial(c.eta0[:, ::-1].copy(), -c.u0[:, ::-1], c.v0[:, ::-1].copy())
+    a.step(40)
+    b.step(40)
+    ha, ua, va = (t.cpu().numpy() for t in a.raw_state())
+    hb, ub, vb = (t.cpu().numpy() for t in b.raw_state())
+    assert np.array_equal(hb, ha[:, ::-1])
+    assert np.array_equal(ub, -ua[:, ::-1])
+    assert np.array_equal(vb, va[:, ::-1])
+
+
+@pytest.mark.parametrize("opts", [dict(sweep_order=1), dict(solver=1), dict(manning_n2=0.0009),
+                                  dict(itopo=0, dwall=5.0)],
+                         ids=["alternate", "solver1", "friction", "wallmode"])
+def test_fp32_options_close_to_oracle(clf, oracle_mod, opts):
+    case = synth.random_small(7, 90, 70, land=True)
+    g = clf.Solver.from_case(case, precision=clf.FP32, **opts)
+    o = oracle_mod.Oracle.from_case(case, **opts)
+    for obj in (g, o):
+        obj.set_initial(2.0 * case.eta0, case.u0, case.v0)
+        obj.step(30)
+    r = fp32_report(g, o)
+    print(opts, r)
+    assert r["max_eta_err"] <= 2e-3 and r["mask_flip"] <= 2e-3
+
+
+def test_fp32_sampling_runs(clf, oracle_mod):
+    case = synth.config1(nx=120, ny=100, steps=10)
+    g = clf.Solver.from_case(case, precision=clf.FP32, gout=2)
+    o = oracle_mod.Oracle.from_case(case, gout=2)
+    ix = np.array([3, 50, 100]); iy = np.array([5, 50, 20])
+    for obj in (g, o):
+        obj.set_initial(2.0 * case.eta0)
+        obj.set_gauges(ix, iy)
+        obj.step(20)
+    rg, _ = g.read_gauges()
+    ro, _ = o.read_gauges()
+    assert rg.shape == ro.shape
+    assert np.abs(rg - ro).max() <= 1e-3 * max(np.abs(ro).max(), 1e-9)
+    mg = g.read_maxwave()[0].cpu().numpy()
+    mo = o.read_maxwave()[0]
+    assert np.abs(mg - mo).max() <= 2e-3 * mo.max()
