@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true", help="short run for profilers")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -113,13 +115,23 @@ def main():
     log("grid %dx%d dt %.4f" % (case.nx, case.ny, case.dt))
     torch.cuda.set_device(0)
 
+    if args.calibrate_copy:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     # --- whole step: fused kernel + gauge records ---
-    s = clf.Solver.from_case(case, precision=prec, gout=10, maxout=1,
+    s = clf.Solver.from_case(case, precision=prec, gout=10, maxout=1, autotune=1,
                              gauge_capacity=(args.steps + args.warmup) // 10 + 8)
     s.set_initial(case.eta0, case.u0, case.v0)
     if case.gauges is not None:
         s.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
-    log("init done; segment %d rows, %d tiles" % (s.query(clf.Q_SEGMENT), s.query(clf.Q_TILES)))
+    seg = int(s.query(clf.Q_SEGMENT))
+    log("init done; segment %d rows, %d tiles" % (seg, s.query(clf.Q_TILES)))
     s.step(args.warmup)
     s.sync()
     secs = time_steps(s, torch, args.steps)
@@ -130,7 +142,7 @@ def main():
     del s
 
     # --- roofline leg: the step kernel alone ---
-    r = clf.Solver.from_case(case, precision=prec, maxout=1)
+    r = clf.Solver.from_case(case, precision=prec, maxout=1, autotune=1)
     r.set_initial(case.eta0, case.u0, case.v0)
     r.step(args.warmup)
     r.sync()
@@ -158,8 +170,8 @@ def main():
                    "nx": case.nx, "ny": case.ny, "dt": case.dt},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": None,
-                     "kernel": "step_kernel (fused x-y march), %d B/cell-step algorithmic"
-                               % (WORDS_PER_CELL_STEP * esize),
+                     "kernel": "step_kernel (fused x-y march), %d B/cell-step algorithmic, "
+                               "segment %d rows" % (WORDS_PER_CELL_STEP * esize, seg),
                      "mean_launch_ms": per_launch * 1e3},
     }
     if not args.no_cpu:
