@@ -38,13 +38,14 @@ constexpr double kG = 9.81;
 // ---------------------------------------------------------------------------
 // Cross-lane exchange: value held by lane-1 / lane+1 of the wavefront, by
 // DPP whole-wave shifts (wave_shr:1 / wave_shl:1).  Lanes without a source
-// (lane 0, lane 63) keep their own value; they lie in the halo.
+// (lane 0, lane 63) read 0 (bound_ctrl); they lie in the halo and a zero
+// flag word makes their neighbour look missing.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_prev_i(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false);
+  return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);
 }
 __device__ __forceinline__ int lane_next_i(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false);
+  return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true);
 }
 
 template <class T>
@@ -210,27 +211,16 @@ struct P64 {
 
   static __device__ __forceinline__ C stage_cd(const Bx& l, const B& c, const Bx& r, double iL,
                                                double iR, double iS, double tanR, const Par& p) {
-    C o;
-    if ((p.flags & (G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N)) && (c.f & F_FIX)) {
-      o.H = c.H; o.w = c.w; o.t = c.t;
-      return o;
-    }
-    if (!(c.f & F_WET)) {
-      o.H = 0.0; o.w = 0.0; o.t = 0.0;
-      return o;
-    }
-    double Lw, Lt, LD, Lc, Rw, Rt, RD, Rc;
-    if ((l.f & (F_EX | F_WET)) == (F_EX | F_WET)) {
-      Lw = l.w; Lt = l.t; LD = l.D; Lc = l.c;
-    } else {
-      Lw = -c.w; Lt = c.t; LD = c.D; Lc = c.c;   // mirror ghost
-    }
-    if ((r.f & (F_EX | F_WET)) == (F_EX | F_WET)) {
-      Rw = r.w; Rt = r.t; RD = r.D; Rc = r.c;
-    } else {
-      Rw = -c.w; Rt = c.t; RD = c.D; Rc = c.c;
-    }
+    // Every lane computes the update; dry and held nodes select their value
+    // at the end (a wet node's result is the same bits either way).
+    const bool lreal = (l.f & (F_EX | F_WET)) == (F_EX | F_WET);
+    const bool rreal = (r.f & (F_EX | F_WET)) == (F_EX | F_WET);
     const double Cw = c.w, Ct = c.t, CD = c.D, Cc = c.c;
+    // mirror ghost (h_k, -w_k, t_k, d_k) where the neighbour is dry or missing
+    const double Lw = lreal ? l.w : -Cw, Lt = lreal ? l.t : Ct, LD = lreal ? l.D : CD,
+                 Lc = lreal ? l.c : Cc;
+    const double Rw = rreal ? r.w : -Cw, Rt = rreal ? r.t : Ct, RD = rreal ? r.D : CD,
+                 Rc = rreal ? r.c : Cc;
     double xPL = Lw + 2.0 * Lc, xPC = Cw + 2.0 * Cc, xPR = Rw + 2.0 * Rc;
     double lPL = Lw + Lc, lPC = Cw + Cc, lPR = Rw + Rc;
     double xML = Lw - 2.0 * Lc, xMC = Cw - 2.0 * Cc, xMR = Rw - 2.0 * Rc;
@@ -260,7 +250,7 @@ struct P64 {
     double ws = Pn + Mn;
     double wv = 0.5 * ws;
     double dd = Pn - Mn;
-    if (dd < 0.0) dd = 0.0;
+    dd = (dd < 0.0) ? 0.0 : dd;
     double Hv = (dd * dd) * p.inv16g;
     if (p.flags & G_FRICTION) {
       double sp = sqrt(Cw * Cw + Ct * Ct);
@@ -268,7 +258,14 @@ struct P64 {
       double fr = ((p.dt * p.gn2) * sp) / den;
       wv = wv / (1.0 + fr);
     }
-    o.H = Hv; o.w = wv; o.t = Tn;
+    const bool wet = (c.f & F_WET) != 0;
+    C o;
+    o.H = wet ? Hv : 0.0;
+    o.w = wet ? wv : 0.0;
+    o.t = wet ? Tn : 0.0;
+    if ((p.flags & (G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N)) && (c.f & F_FIX)) {
+      o.H = c.H; o.w = c.w; o.t = c.t;
+    }
     return o;
   }
 
@@ -280,22 +277,14 @@ struct P64 {
 
   static __device__ __forceinline__ void stage_e(C& o, const Cx& l, const Cx& r, int src,
                                                  double /*D*/) {
-    if (src == 0) return;
-    if (src == 2) {
-      double a = l.H, b = r.H;
-      double m = (b < a) ? b : a;
-      double cap = 0.5 * m;
-      if (o.H > cap) o.H = cap;
-      return;
-    }
-    const Cx& s = (src == -1) ? l : r;
-    double cap = 0.5 * s.H;
-    if (o.H > cap) o.H = cap;
-    if (src == -1) {
-      if (o.w > s.w) o.w = s.w;
-    } else {
-      if (o.w < s.w) o.w = s.w;
-    }
+    // source on the left (src -1), right (+1), tie (2) or none (0)
+    const double m = (r.H < l.H) ? r.H : l.H;
+    const double sh = (src == -1) ? l.H : r.H;
+    const double cap = 0.5 * ((src == 2) ? m : sh);
+    o.H = (src != 0 && o.H > cap) ? cap : o.H;
+    const double sw = (src == -1) ? l.w : r.w;
+    const bool capw = (src == -1) ? (o.w > sw) : ((src == 1) && (o.w < sw));
+    o.w = capw ? sw : o.w;
   }
 
   static __device__ __forceinline__ bool wet_out(const C& o, double /*D*/, const Par& p) {
@@ -320,7 +309,7 @@ struct P32 {
   static constexpr float kGf = 9.81f;
   struct A { float H, w, t, D; int f; int pad; };          // H = eta
   struct B { float H, w, t, D, c, h; int f; int src; };   // h = total height
-  struct Bx { float w, t, D, c, H, h; int f; int pad; };
+  struct Bx { float w, t, D, c, H; int f; };
   struct C { float H, w, t, h; };                         // eta', u', v', h'
   struct Cx { float h, w; };
 
@@ -390,12 +379,12 @@ struct P32 {
   }
 
   static __device__ __forceinline__ void set_c(B& b) {
-    b.c = (b.f & F_WET) ? sqrtf(kGf * b.h) : 0.f;
+    b.c = (b.f & F_WET) ? __builtin_amdgcn_sqrtf(kGf * b.h) : 0.f;
   }
 
   static __device__ __forceinline__ Bx bx(const B& b) {
     Bx x;
-    x.w = b.w; x.t = b.t; x.D = b.D; x.c = b.c; x.H = b.H; x.h = b.h; x.f = b.f; x.pad = 0;
+    x.w = b.w; x.t = b.t; x.D = b.D; x.c = b.c; x.H = b.H; x.f = b.f;
     return x;
   }
 
@@ -409,7 +398,7 @@ struct P32 {
     const float lam2 = sw + sg * sc;
     const float adv = 0.5f * lam2 * dw;
     const float grav = kGf * de;
-    const float cross = kGf * dh * (sw / sc);
+    const float cross = kGf * dh * (sw * __builtin_amdgcn_rcpf(sc));
     return (adv + grav + sg * cross) * inv;
   }
 
@@ -425,27 +414,14 @@ struct P32 {
 
   static __device__ __forceinline__ C stage_cd(const Bx& l, const B& c, const Bx& r, float iL,
                                                float iR, float iS, float tanR, const Par& p) {
-    C o;
-    if ((p.flags & (G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N)) && (c.f & F_FIX)) {
-      o.H = c.H; o.w = c.w; o.t = c.t; o.h = c.h;
-      return o;
-    }
-    if (!(c.f & F_WET)) {
-      o.H = -c.D; o.w = 0.f; o.t = 0.f; o.h = 0.f;
-      return o;
-    }
-    float Lw, Lt, LD, Lc, Le, Rw, Rt, RD, Rc, Re;
-    if ((l.f & (F_EX | F_WET)) == (F_EX | F_WET)) {
-      Lw = l.w; Lt = l.t; LD = l.D; Lc = l.c; Le = l.H;
-    } else {
-      Lw = -c.w; Lt = c.t; LD = c.D; Lc = c.c; Le = c.H;   // mirror ghost
-    }
-    if ((r.f & (F_EX | F_WET)) == (F_EX | F_WET)) {
-      Rw = r.w; Rt = r.t; RD = r.D; Rc = r.c; Re = r.H;
-    } else {
-      Rw = -c.w; Rt = c.t; RD = c.D; Rc = c.c; Re = c.H;
-    }
+    const bool lreal = (l.f & (F_EX | F_WET)) == (F_EX | F_WET);
+    const bool rreal = (r.f & (F_EX | F_WET)) == (F_EX | F_WET);
     const float Cw = c.w, Ct = c.t, CD = c.D, Cc = c.c, Ce = c.H;
+    // mirror ghost where the neighbour is dry or missing
+    const float Lw = lreal ? l.w : -Cw, Lt = lreal ? l.t : Ct, LD = lreal ? l.D : CD,
+                Lc = lreal ? l.c : Cc, Le = lreal ? l.H : Ce;
+    const float Rw = rreal ? r.w : -Cw, Rt = rreal ? r.t : Ct, RD = rreal ? r.D : CD,
+                Rc = rreal ? r.c : Cc, Re = rreal ? r.H : Ce;
     const float QPL = qpm(1.f, Lw, Lc, Le, LD, Cw, Cc, Ce, CD, iL);
     const float QPR = qpm(1.f, Cw, Cc, Ce, CD, Rw, Rc, Re, RD, iR);
     const float QML = qpm(-1.f, Lw, Lc, Le, LD, Cw, Cc, Ce, CD, iL);
@@ -468,22 +444,25 @@ struct P32 {
     }
     float wv = Cw + 0.5f * (dP + dM);
     const float dd = dP - dM;
-    float hv, ev;
-    if (4.f * Cc + dd < 0.f) {
-      hv = 0.f;
-      ev = -CD;
-    } else {
-      const float dh = (dd * (8.f * Cc + dd)) * p.inv16g;
-      hv = c.h + dh;
-      ev = Ce + dh;
-    }
+    const float dh = (dd * (8.f * Cc + dd)) * p.inv16g;
+    const bool drained = 4.f * Cc + dd < 0.f;
+    const float hv = drained ? 0.f : c.h + dh;
+    const float ev = drained ? -CD : Ce + dh;
     if (p.flags & G_FRICTION) {
       const float sp = sqrtf(Cw * Cw + Ct * Ct);
       const float den = c.h * cbrtf(c.h);
       const float fr = ((p.dt * p.gn2) * sp) / den;
       wv = wv / (1.f + fr);
     }
-    o.H = ev; o.w = wv; o.t = Ct + dT; o.h = hv;
+    const bool wet = (c.f & F_WET) != 0;
+    C o;
+    o.H = wet ? ev : -CD;
+    o.w = wet ? wv : 0.f;
+    o.t = wet ? Ct + dT : 0.f;
+    o.h = wet ? hv : 0.f;
+    if ((p.flags & (G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N)) && (c.f & F_FIX)) {
+      o.H = c.H; o.w = c.w; o.t = c.t; o.h = c.h;
+    }
     return o;
   }
 
@@ -495,24 +474,15 @@ struct P32 {
 
   static __device__ __forceinline__ void stage_e(C& o, const Cx& l, const Cx& r, int src,
                                                  float D) {
-    if (src == 0) return;
-    float cap;
-    if (src == 2) {
-      const float m = (r.h < l.h) ? r.h : l.h;
-      cap = 0.5f * m;
-    } else {
-      const Cx& s = (src == -1) ? l : r;
-      cap = 0.5f * s.h;
-      if (src == -1) {
-        if (o.w > s.w) o.w = s.w;
-      } else {
-        if (o.w < s.w) o.w = s.w;
-      }
-    }
-    if (o.h > cap) {
-      o.h = cap;
-      o.H = cap - D;
-    }
+    const float m = (r.h < l.h) ? r.h : l.h;
+    const float sh = (src == -1) ? l.h : r.h;
+    const float cap = 0.5f * ((src == 2) ? m : sh);
+    const bool caph = src != 0 && o.h > cap;
+    o.h = caph ? cap : o.h;
+    o.H = caph ? cap - D : o.H;
+    const float sw = (src == -1) ? l.w : r.w;
+    const bool capw = (src == -1) ? (o.w > sw) : ((src == 1) && (o.w < sw));
+    o.w = capw ? sw : o.w;
   }
 
   static __device__ __forceinline__ bool wet_out(const C& o, float D, const Par& p) {
@@ -580,7 +550,7 @@ __device__ __forceinline__ typename P::C xsweep_row(typename P::A a, typename P:
     typename P::Cx cc = P::cx(c);
     typename P::Cx cl = from_prev(cc);
     typename P::Cx cr = from_next(cc);
-    if (b.f & F_EX) P::stage_e(c, cl, cr, b.src, b.D);
+    P::stage_e(c, cl, cr, b.src, b.D);
   }
   return c;
 }
@@ -617,8 +587,12 @@ __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_i
   constexpr int K1 = (K + 1) % 3, K2 = (K + 2) % 3;
   y.a[K] = a_in;
   P::stage_a(y.a[K], cx.par);
-  // (b) on row r-1
-  y.b[K] = P::stage_b(y.a[K1], y.a[K2], y.a[K], cx.par);
+  // (b) on row r-1 (centre a[K2]); the flooding logic runs only when some
+  // lane of the wavefront has a dry node next to a wet one
+  if (__ballot(P::flood_candidate(y.a[K2].f, y.a[K1].f, y.a[K].f)) != 0)
+    y.b[K] = P::stage_b(y.a[K1], y.a[K2], y.a[K], cx.par);
+  else
+    y.b[K] = P::stage_b_copy(y.a[K2]);
   P::set_c(y.b[K]);
   // (c)+(d) on row r-2
   const int rc = r - 2;
@@ -633,7 +607,7 @@ __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_i
   // (e) on row r-3
   out = y.c[K2];
   ob = y.b[K1];
-  if (ob.src != 0) P::stage_e(out, P::cx(y.c[K1]), P::cx(y.c[K]), ob.src, ob.D);
+  if (__ballot(ob.src != 0) != 0) P::stage_e(out, P::cx(y.c[K1]), P::cx(y.c[K]), ob.src, ob.D);
 }
 
 // FL: the grid flags this instantiation honours (others are compiled out).
@@ -664,6 +638,7 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
     tl.x0 = __builtin_amdgcn_readfirstlane(tl.x0);
     tl.y0 = __builtin_amdgcn_readfirstlane(tl.y0);
     tl.rows = __builtin_amdgcn_readfirstlane(tl.rows);
+    if (tl.rows <= 0) return;   // padding slot of the XCD-aware order
     const GridDesc& g = grids[tl.grid];
     Ctx<P> cx;
     cx.H = (const R*)g.H[parity];
@@ -705,25 +680,26 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
     }
     int bad = 0;
 
+    // Loads use clamped, always in-bounds indices; nodes outside the grid
+    // only lose their existence flag (no divergent branches, no zero fill).
+    const int xcl = xc < 0 ? 0 : (xc >= nx ? nx - 1 : xc);
     auto load_row = [&](int r, A& a) {
-      a.f = 0;
-      a.H = 0; a.w = 0; a.t = 0; a.D = 0;
-      if (r >= 0 && r < ny && col_in) {
-        const long long k = (long long)r * nx + xc;
-        a.H = gload(cx.H + k);
-        a.D = gload(cx.D + k);
-        a.w = gload(cx.U + k);   // x view: w = u, t = v
-        a.t = gload(cx.V + k);
-        a.f = F_EX;
-        if (kRing) a.f |= ring_flag(cx.gflags, xc, r, nx, ny);
-      }
+      const int rc = r < 0 ? 0 : (r >= ny ? ny - 1 : r);
+      const long long k = (long long)rc * nx + xcl;
+      a.H = gload(cx.H + k);
+      a.D = gload(cx.D + k);
+      a.w = gload(cx.U + k);   // x view: w = u, t = v
+      a.t = gload(cx.V + k);
+      a.f = (col_in && r >= 0 && r < ny) ? F_EX : 0;
+      if (kRing) a.f |= ring_flag(cx.gflags, xc, r, nx, ny);
     };
     // maxwave values of an output row, read one march row ahead of use
     struct MW { R e, s2; };
     auto load_mw = [&](int r, MW& m) {
       m.e = 0; m.s2 = 0;
-      if (do_max && out_lane && r >= 0 && r < ny) {
-        const long long k = (long long)r * nx + xc;
+      if (do_max) {
+        const int rc = r < 0 ? 0 : (r >= ny ? ny - 1 : r);
+        const long long k = (long long)rc * nx + xcl;
         m.e = gload(cx.emax + k);
         m.s2 = gload(cx.smax2 + k);
       }

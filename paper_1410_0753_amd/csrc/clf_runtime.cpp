@@ -65,7 +65,7 @@ Layout plan(int nx, int ny, const clf_params& p) {
   L.st = take(sizeof(StepState));
   L.sd = take(sizeof(SampleDesc));
   L.fd = take(sizeof(ForceDesc));
-  L.ntiles_max = strips_of(nx) * ((ny + kMinSeg - 1) / kMinSeg);
+  L.ntiles_max = strips_of(nx) * ((ny + kMinSeg - 1) / kMinSeg) + 8 * WAVES_PER_BLOCK * 2;
   L.tiles = take(sizeof(Tile) * (size_t)L.ntiles_max);
   for (int i = 0; i < 9; ++i) L.f[i] = take(es * N);
   L.xib = take(es * (nx + 1));
@@ -239,29 +239,65 @@ hipError_t upload_any(int fp32, const std::vector<double>& v, void* dst, hipStre
   return fp32 ? upload<float>(v, dst, s) : upload<double>(v, dst, s);
 }
 
-int build_tiles(clf_ctx* c, int seg) {
-  const int ns = strips_of(c->nx);
-  const int nsegs = (c->ny + seg - 1) / seg;
-  std::vector<Tile> t;
-  t.reserve((size_t)ns * nsegs);
+// Natural tile order: segment rows top to bottom, strips left to right.
+void natural_tiles(int grid, int nx, int ny, int seg, std::vector<Tile>& t) {
+  const int ns = strips_of(nx);
+  const int nsegs = (ny + seg - 1) / seg;
   for (int q = 0; q < nsegs; ++q)
     for (int s = 0; s < ns; ++s) {
       Tile tl;
-      tl.grid = 0;
+      tl.grid = grid;
       tl.x0 = s * STRIP;
       tl.y0 = q * seg;
-      tl.rows = std::min(seg, c->ny - q * seg);
+      tl.rows = std::min(seg, ny - q * seg);
       t.push_back(tl);
     }
+}
+
+// XCD-aware order.  Workgroups are dispatched round-robin over the 8 XCDs
+// (workgroup b runs on XCD b % 8), each with its own L2.  The natural list
+// is cut into 8 contiguous chunks and chunk x is dealt to the workgroups of
+// XCD x, so tiles that share halo rows and columns meet in the same L2.
+// Slots past the end of a chunk carry rows = 0 (no work).
+constexpr int kXcds = 8;
+
+std::vector<Tile> xcd_order(const std::vector<Tile>& nat, int* nblocks) {
+  const int n = (int)nat.size();
+  const int per = (n + kXcds - 1) / kXcds;
+  const int bper = (per + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;  // blocks per XCD
+  std::vector<Tile> out((size_t)bper * kXcds * WAVES_PER_BLOCK);
+  for (int b = 0; b < bper * kXcds; ++b) {
+    const int x = b % kXcds, j = b / kXcds;
+    for (int w = 0; w < WAVES_PER_BLOCK; ++w) {
+      const int li = j * WAVES_PER_BLOCK + w;
+      const int gi = x * per + li;
+      Tile tl{0, 0, 0, 0};
+      if (li < per && gi < n) tl = nat[gi];
+      out[(size_t)b * WAVES_PER_BLOCK + w] = tl;
+    }
+  }
+  *nblocks = bper * kXcds;
+  return out;
+}
+
+int upload_tiles(clf_ctx* c, const std::vector<Tile>& t, int nblocks, int seg) {
   if ((int)t.size() > c->L.ntiles_max)
-    return fail(c, CLF_EINVAL, "segment %d too short (minimum %d rows)", seg, kMinSeg);
+    return fail(c, CLF_EINVAL, "segment %d too short for the tile table", seg);
   HIPCHK(c, hipMemcpyAsync(c->tiles_dev, t.data(), t.size() * sizeof(Tile),
                            hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->ntiles = (int)t.size();
-  c->nblocks = (c->ntiles + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  c->nblocks = nblocks;
   c->seg = seg;
   return CLF_OK;
+}
+
+int build_tiles(clf_ctx* c, int seg) {
+  std::vector<Tile> nat;
+  natural_tiles(0, c->nx, c->ny, seg, nat);
+  int nb = 0;
+  std::vector<Tile> t = xcd_order(nat, &nb);
+  return upload_tiles(c, t, nb, seg);
 }
 
 int default_segment(int nx, int ny) {
