@@ -78,6 +78,8 @@ extern "C" {
 #define CLF_Q_GAUGE_RECORDS 6  /* gauge records held */
 #define CLF_Q_TILES 7          /* wavefront tiles per step kernel launch */
 #define CLF_Q_SEGMENT 8        /* rows per wavefront tile (autotuned) */
+#define CLF_Q_BLOCKS 9         /* workgroups per step kernel launch */
+#define CLF_Q_GRAPH_REPLAYS 10 /* hipGraph replays issued so far */
 
 typedef struct clf_ctx clf_ctx;
 
@@ -119,6 +121,11 @@ typedef struct clf_params {
   int32_t segment;          /* rows per wavefront tile of the step kernel; 0 = automatic */
   int32_t autotune;         /* 1: clf_init times candidate tile shapes on this grid and keeps
                                the fastest (cached per grid size and precision in the process) */
+  int32_t graph_steps;      /* >0: step sequences that do not depend on the step index (no
+                               forcing, no gauges or series, maxout 1, x-y order) run as
+                               replays of a hipGraph holding this many steps (even); 0: off */
+  int32_t persistent_blocks; /* >0: the step kernel runs this many workgroups (a multiple of 8)
+                               looping over the tiles; 0: one wavefront per tile */
 } clf_params;
 
 void clf_default_params(clf_params* p);
@@ -218,6 +225,45 @@ const char* clf_last_error(const clf_ctx* c);
 
 /* Free host-side resources.  The workspace stays the caller's. */
 int clf_destroy(clf_ctx* c);
+
+/* ------------------------------------------------------------------------
+ * Ensemble: many independent grids (scenarios) of uneven sizes advanced in
+ * lockstep.  Each time step is ONE launch of the step kernel over the
+ * concatenated tile list of all members (XCD-aware order, optionally a
+ * persistent grid-stride launch), and step chunks are replayed from a
+ * hipGraph when p->graph_steps > 0 and maxout == 1.  Every member computes
+ * exactly what a single-grid context would (bit for bit).  Members have
+ * their own grid, depth and dt and share the parameters; gauges, series
+ * and forcing are not available on ensemble members (maxwave is).
+ * ------------------------------------------------------------------------ */
+typedef struct clf_ens clf_ens;
+
+/* Workspace for n members (grids[i] as for clf_init). */
+int clf_ensemble_workspace_bytes(int n, const clf_grid* grids, const clf_params* p,
+                                 size_t* bytes);
+
+/* depths[i]: host [ny_i][nx_i]; dts[i]: member time step.  Each member is
+ * preprocessed and checked as by clf_init and starts as the lake at rest. */
+int clf_ensemble_init(clf_ens** out, int n, const clf_grid* grids, const double* const* depths,
+                      const double* dts, const clf_params* p, void* stream, void* ws,
+                      size_t ws_bytes);
+
+/* Initial condition of one member (as clf_set_initial); resets its maxwave. */
+int clf_ensemble_set_initial(clf_ens* e, int member, const double* eta, const double* u,
+                             const double* v, int deform_bottom);
+
+/* Advance every member nsteps steps.  Asynchronous. */
+int clf_ensemble_step(clf_ens* e, int nsteps);
+
+/* Per-member read-outs (device arrays of that member's shape). */
+int clf_ensemble_get_state(clf_ens* e, int member, double* eta, double* u, double* v,
+                           uint8_t* wet);
+int clf_ensemble_read_maxwave(clf_ens* e, int member, double* eta_max, double* speed_max);
+
+int clf_ensemble_sync(clf_ens* e);
+int clf_ensemble_query(clf_ens* e, int what, double* value);
+const char* clf_ensemble_last_error(const clf_ens* e);
+int clf_ensemble_destroy(clf_ens* e);
 
 #ifdef __cplusplus
 }

@@ -23,14 +23,19 @@ CARTESIAN, SPHERICAL = 0, 1
 FP64, FP32 = 0, 1
 ORDER_XY, ORDER_ALTERNATE = 0, 1
 WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
-Q_MAX_CFL, Q_SSL_PASSES, Q_STEP, Q_MIN_F, Q_WORKSPACE, Q_GAUGE_RECORDS, Q_TILES, Q_SEGMENT = range(1, 9)
+(Q_MAX_CFL, Q_SSL_PASSES, Q_STEP, Q_MIN_F, Q_WORKSPACE, Q_GAUGE_RECORDS, Q_TILES, Q_SEGMENT,
+ Q_BLOCKS, Q_GRAPH_REPLAYS) = range(1, 11)
 
 # Every symbol include/clf.h declares.
 EXPORTS = ["clf_default_params", "clf_workspace_bytes", "clf_init", "clf_set_initial",
            "clf_set_raw_state", "clf_get_raw_state", "clf_set_boundary_forcing", "clf_set_gauges",
            "clf_add_enclosed_grid", "clf_step", "clf_sweep", "clf_get_state", "clf_get_depth",
            "clf_read_gauges", "clf_read_maxwave", "clf_read_boundary_series",
-           "clf_clear_records", "clf_sync", "clf_query", "clf_last_error", "clf_destroy"]
+           "clf_clear_records", "clf_sync", "clf_query", "clf_last_error", "clf_destroy",
+           "clf_ensemble_workspace_bytes", "clf_ensemble_init", "clf_ensemble_set_initial",
+           "clf_ensemble_step", "clf_ensemble_get_state", "clf_ensemble_read_maxwave",
+           "clf_ensemble_sync", "clf_ensemble_query", "clf_ensemble_last_error",
+           "clf_ensemble_destroy"]
 
 
 class ClfError(RuntimeError):
@@ -53,7 +58,8 @@ class Params(C.Structure):
                 ("bndout", C.c_int32), ("max_gauges", C.c_int32), ("gauge_capacity", C.c_int32),
                 ("max_enclosed", C.c_int32), ("max_enclosed_points", C.c_int32),
                 ("series_capacity", C.c_int32), ("forcing_capacity", C.c_int32),
-                ("segment", C.c_int32), ("autotune", C.c_int32)]
+                ("segment", C.c_int32), ("autotune", C.c_int32),
+                ("graph_steps", C.c_int32), ("persistent_blocks", C.c_int32)]
 
 
 _lock = threading.Lock()
@@ -96,6 +102,17 @@ def load(build_if_missing: bool = True):
             "clf_query": (i32, [vp, i32, C.POINTER(dbl)]),
             "clf_last_error": (C.c_char_p, [vp]),
             "clf_destroy": (i32, [vp]),
+            "clf_ensemble_workspace_bytes": (i32, [i32, vp, C.POINTER(Params), C.POINTER(C.c_size_t)]),
+            "clf_ensemble_init": (i32, [C.POINTER(vp), i32, vp, vp, vp, C.POINTER(Params), vp, vp,
+                                        C.c_size_t]),
+            "clf_ensemble_set_initial": (i32, [vp, i32, vp, vp, vp, i32]),
+            "clf_ensemble_step": (i32, [vp, i32]),
+            "clf_ensemble_get_state": (i32, [vp, i32, vp, vp, vp, vp]),
+            "clf_ensemble_read_maxwave": (i32, [vp, i32, vp, vp]),
+            "clf_ensemble_sync": (i32, [vp]),
+            "clf_ensemble_query": (i32, [vp, i32, C.POINTER(dbl)]),
+            "clf_ensemble_last_error": (C.c_char_p, [vp]),
+            "clf_ensemble_destroy": (i32, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -287,4 +304,96 @@ class Solver:
     def query(self, what):
         v = C.c_double(0)
         self._check(load().clf_query(self._h, int(what), C.byref(v)))
+        return v.value
+
+
+class Ensemble:
+    """Many grids advanced in lockstep by one step-kernel launch per step."""
+
+    def __init__(self, cases, precision=FP64, device=None, stream=None, **params):
+        import torch
+        self.torch = torch
+        L = load()
+        self.device = torch.device(device or "cuda")
+        n = len(cases)
+        self._keep = []
+        grids = (Grid * n)()
+        depths = (C.c_void_p * n)()
+        dts = (C.c_double * n)()
+        self.shapes = []
+        for i, cs in enumerate(cases):
+            x, y, d = _np64(cs.x), _np64(cs.y), _np64(cs.depth)
+            self._keep += [x, y, d]
+            grids[i] = Grid(d.shape[1], d.shape[0], cs.coord, x.ctypes.data_as(C.POINTER(C.c_double)),
+                            y.ctypes.data_as(C.POINTER(C.c_double)))
+            depths[i] = d.ctypes.data_as(C.c_void_p)
+            dts[i] = float(cs.dt)
+            self.shapes.append(d.shape)
+        params.setdefault("h_min", cases[0].h_min)
+        self.params = default_params(precision=precision, **params)
+        nbytes = C.c_size_t(0)
+        rc = L.clf_ensemble_workspace_bytes(n, grids, C.byref(self.params), C.byref(nbytes))
+        self._chk(rc, None)
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        rc = L.clf_ensemble_init(C.byref(h), n, grids, depths, dts, C.byref(self.params),
+                                 C.c_void_p(self.stream.cuda_stream),
+                                 C.c_void_p(self.workspace.data_ptr()), nbytes.value)
+        self._chk(rc, None)
+        self._h = h
+        self.n = n
+
+    def _chk(self, rc, h):
+        if rc != CLF_OK:
+            raise ClfError(rc, load().clf_ensemble_last_error(h).decode())
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.clf_ensemble_destroy(h)
+            self._h = None
+
+    def _dev64(self, a, shape):
+        if a is None:
+            return None
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            a = a.to(device=self.device, dtype=t.float64)
+        else:
+            a = t.from_numpy(_np64(a)).to(self.device)
+        return a.reshape(shape).contiguous()
+
+    def set_initial(self, member, eta=None, u=None, v=None, deform_bottom=False):
+        sh = self.shapes[member]
+        e, uu, vv = (self._dev64(a, sh) for a in (eta, u, v))
+        self._chk(load().clf_ensemble_set_initial(self._h, member, _dptr(e), _dptr(uu), _dptr(vv),
+                                                  int(bool(deform_bottom))), self._h)
+        self.torch.cuda.synchronize(self.device)
+
+    def step(self, n=1):
+        self._chk(load().clf_ensemble_step(self._h, int(n)), self._h)
+
+    def sync(self):
+        self._chk(load().clf_ensemble_sync(self._h), self._h)
+
+    def state(self, member):
+        t = self.torch
+        sh = self.shapes[member]
+        e, u, v = (t.empty(sh, dtype=t.float64, device=self.device) for _ in range(3))
+        w = t.empty(sh, dtype=t.uint8, device=self.device)
+        self._chk(load().clf_ensemble_get_state(self._h, member, _dptr(e), _dptr(u), _dptr(v),
+                                                _dptr(w)), self._h)
+        return e, u, v, w
+
+    def read_maxwave(self, member):
+        t = self.torch
+        sh = self.shapes[member]
+        e, s = (t.empty(sh, dtype=t.float64, device=self.device) for _ in range(2))
+        self._chk(load().clf_ensemble_read_maxwave(self._h, member, _dptr(e), _dptr(s)), self._h)
+        return e, s
+
+    def query(self, what):
+        v = C.c_double(0)
+        self._chk(load().clf_ensemble_query(self._h, int(what), C.byref(v)), self._h)
         return v.value

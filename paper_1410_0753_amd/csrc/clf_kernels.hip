@@ -631,14 +631,17 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
   // the wave index is uniform across the wavefront: say so, so that the
   // tile, the row counter and the row metrics live in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-  const int tid = blockIdx.x * WAVES_PER_BLOCK + wave;
-  if (tid < ntiles) {
+  // grid-stride over the tile list: one tile per wavefront when the grid
+  // covers the list, a persistent loop when it is launched smaller
+  const int stride = gridDim.x * WAVES_PER_BLOCK;
+  int bad = 0;
+  for (int tid = blockIdx.x * WAVES_PER_BLOCK + wave; tid < ntiles; tid += stride) {
     Tile tl = tiles[tid];
     tl.grid = __builtin_amdgcn_readfirstlane(tl.grid);
     tl.x0 = __builtin_amdgcn_readfirstlane(tl.x0);
     tl.y0 = __builtin_amdgcn_readfirstlane(tl.y0);
     tl.rows = __builtin_amdgcn_readfirstlane(tl.rows);
-    if (tl.rows <= 0) return;   // padding slot of the XCD-aware order
+    if (tl.rows <= 0) continue;   // padding slot of the XCD-aware order
     const GridDesc& g = grids[tl.grid];
     Ctx<P> cx;
     cx.H = (const R*)g.H[parity];
@@ -678,8 +681,6 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
       xiR = gload((const R*)g.xib + xc + 1);
       xiS = gload((const R*)g.xisb + xc);
     }
-    int bad = 0;
-
     // Loads use clamped, always in-bounds indices; nodes outside the grid
     // only lose their existence flag (no divergent branches, no zero fill).
     const int xcl = xc < 0 ? 0 : (xc >= nx ? nx - 1 : xc);
@@ -794,8 +795,8 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
         if (r + 2 < r_end) body(std::integral_constant<int, 2>(), r + 2);
       }
     }
-    if (bad) st->bad = 1;
   }
+  if (bad) st->bad = 1;
 }
 
 // ---------------------------------------------------------------------------

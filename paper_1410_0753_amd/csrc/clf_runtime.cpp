@@ -124,6 +124,9 @@ struct clf_ctx {
   int npts = 0, rec_len = 0;
   long long s_first = 0;
   bool forcing = false;
+  hipStream_t cap_stream = nullptr;   // capture-only stream (never runs work)
+  hipGraphExec_t graph = nullptr;     // graph_steps steps starting from buffer 0
+  long long graph_replays = 0;
   std::string err;
 };
 
@@ -281,6 +284,10 @@ std::vector<Tile> xcd_order(const std::vector<Tile>& nat, int* nblocks) {
 }
 
 int upload_tiles(clf_ctx* c, const std::vector<Tile>& t, int nblocks, int seg) {
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
   if ((int)t.size() > c->L.ntiles_max)
     return fail(c, CLF_EINVAL, "segment %d too short for the tile table", seg);
   HIPCHK(c, hipMemcpyAsync(c->tiles_dev, t.data(), t.size() * sizeof(Tile),
@@ -448,6 +455,8 @@ void clf_default_params(clf_params* p) {
   p->forcing_capacity = 0;
   p->segment = 0;
   p->autotune = 0;
+  p->graph_steps = 16;
+  p->persistent_blocks = 0;
 }
 
 static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c) {
@@ -486,6 +495,10 @@ static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c) {
     return fail(c, CLF_EINVAL, "negative capacity");
   if (p->earth_radius <= 0.0) return fail(c, CLF_EINVAL, "earth_radius must be > 0");
   if (p->segment < 0 || p->segment > 4096) return fail(c, CLF_EINVAL, "segment out of range");
+  if (p->graph_steps < 0 || (p->graph_steps % 2) != 0 || p->graph_steps > 4096)
+    return fail(c, CLF_EINVAL, "graph_steps must be an even number in [0, 4096]");
+  if (p->persistent_blocks < 0 || (p->persistent_blocks % 8) != 0)
+    return fail(c, CLF_EINVAL, "persistent_blocks must be a non-negative multiple of 8");
   return CLF_OK;
 }
 
@@ -497,8 +510,11 @@ int clf_workspace_bytes(const clf_grid* g, const clf_params* p, size_t* bytes) {
   return CLF_OK;
 }
 
-int clf_init(clf_ctx** out, const clf_grid* g, const double* depth, double dt,
-             const clf_params* p, void* stream, void* ws, size_t ws_bytes) {
+// Set up one grid context in a workspace region.  with_tiles: build the
+// context's own tile list (and autotune); ensemble members skip it.
+static int ctx_create(clf_ctx** out, const clf_grid* g, const double* depth, double dt,
+                      const clf_params* p, void* stream, void* ws, size_t ws_bytes,
+                      bool with_tiles) {
   if (!out) return fail(nullptr, CLF_EINVAL, "null output");
   *out = nullptr;
   int rc = validate(g, p, nullptr);
@@ -659,13 +675,13 @@ int clf_init(clf_ctx** out, const clf_grid* g, const double* depth, double dt,
     if (e2 != hipSuccess) r2 = fail(c, CLF_EHIP, "forcing table upload failed");
   }
   int seg = p->segment > 0 ? p->segment : default_segment(c->nx, c->ny);
-  if (r2 == CLF_OK) r2 = build_tiles(c, seg);
+  if (r2 == CLF_OK && with_tiles) r2 = build_tiles(c, seg);
   if (r2 == CLF_OK) {
     // lake at rest: h = max(d, 0), dry at or below h_min
     c->have_state = true;
     r2 = clf_set_initial(c, nullptr, nullptr, nullptr, 0);
   }
-  if (r2 == CLF_OK && p->autotune && p->segment <= 0) {
+  if (r2 == CLF_OK && with_tiles && p->autotune && p->segment <= 0) {
     r2 = autotune_segment(c, &seg);
     if (r2 == CLF_OK) r2 = build_tiles(c, seg);
     if (r2 == CLF_OK) r2 = clf_set_initial(c, nullptr, nullptr, nullptr, 0);
@@ -677,6 +693,11 @@ int clf_init(clf_ctx** out, const clf_grid* g, const double* depth, double dt,
   }
   *out = c;
   return CLF_OK;
+}
+
+int clf_init(clf_ctx** out, const clf_grid* g, const double* depth, double dt,
+             const clf_params* p, void* stream, void* ws, size_t ws_bytes) {
+  return ctx_create(out, g, depth, dt, p, stream, ws, ws_bytes, true);
 }
 
 int clf_set_initial(clf_ctx* c, const double* eta, const double* u, const double* v,
@@ -854,6 +875,34 @@ int clf_add_enclosed_grid(clf_ctx* c, int nx, int ny, const double* x, const dou
   return CLF_OK;
 }
 
+static int eff_blocks(int nblocks, int persistent) {
+  return (persistent > 0 && persistent < nblocks) ? persistent : nblocks;
+}
+
+// Capture graph_steps consecutive steps (buffer 0 -> ... -> buffer 0) into a
+// hipGraph on a capture-only stream.  The sequence is valid for any step
+// index when it does not depend on it (checked by the caller).
+static int build_graph(int fp32, int order, int gflags, const GridDesc* gd, const Tile* tiles,
+                       int ntiles, StepState* st, int nblocks, int steps, hipStream_t* cap,
+                       hipGraphExec_t* exec, clf_ctx* c) {
+  if (!*cap) HIPCHK(c, hipStreamCreateWithFlags(cap, hipStreamNonBlocking));
+  HIPCHK(c, hipStreamBeginCapture(*cap, hipStreamCaptureModeThreadLocal));
+  int cur = 0;
+  hipError_t le = hipSuccess;
+  for (int k = 0; k < steps && le == hipSuccess; ++k) {
+    le = launch_step(fp32, order, gflags, gd, tiles, ntiles, st, cur, 1, nblocks, *cap);
+    cur ^= 1;
+  }
+  hipGraph_t g = nullptr;
+  hipError_t ee = hipStreamEndCapture(*cap, &g);
+  if (le != hipSuccess) return fail(c, CLF_EHIP, "launch during capture: %s", hipGetErrorString(le));
+  if (ee != hipSuccess) return fail(c, CLF_EHIP, "end capture: %s", hipGetErrorString(ee));
+  hipError_t ie = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) return fail(c, CLF_EHIP, "graph instantiate: %s", hipGetErrorString(ie));
+  return CLF_OK;
+}
+
 static int launch_sampling(clf_ctx* c) {
   const bool g = c->ngauge > 0 && c->n % c->p.gout == 0 && c->n >= c->g_first;
   const bool e = c->npts > 0 && c->n % c->p.bndout == 0 && c->n >= c->s_first;
@@ -896,15 +945,32 @@ int clf_step(clf_ctx* c, int nsteps) {
     if (rc) return rc;
     c->rec0 = true;
   }
-  for (int k = 0; k < nsteps; ++k) {
+  const bool graphable = c->p.graph_steps > 0 && !c->forcing && c->ngauge == 0 && c->npts == 0 &&
+                         c->p.maxout == 1 && c->p.sweep_order == CLF_ORDER_XY;
+  const int nb = eff_blocks(c->nblocks, c->p.persistent_blocks);
+  int k = 0;
+  while (k < nsteps) {
+    if (graphable && c->cur == 0 && nsteps - k >= c->p.graph_steps) {
+      if (!c->graph) {
+        rc = build_graph(c->fp32, step_order(c), c->gd.flags, c->gd_dev, c->tiles_dev, c->ntiles,
+                         c->st_dev, nb, c->p.graph_steps, &c->cap_stream, &c->graph, c);
+        if (rc) return rc;
+      }
+      HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+      c->graph_replays += 1;
+      c->n += c->p.graph_steps;
+      k += c->p.graph_steps;
+      continue;
+    }
     if (c->forcing)
       HIPCHK(c, launch_forcing(c->fp32, c->gd_dev, c->fd_dev, std::max(c->nx, c->ny), c->n,
                                c->cur, c->stream));
     const int do_max = ((c->n + 1) % c->p.maxout) == 0;
     HIPCHK(c, launch_step(c->fp32, step_order(c), c->gd.flags, c->gd_dev, c->tiles_dev, c->ntiles,
-                          c->st_dev, c->cur, do_max, c->nblocks, c->stream));
+                          c->st_dev, c->cur, do_max, nb, c->stream));
     c->cur ^= 1;
     c->n += 1;
+    ++k;
     rc = launch_sampling(c);
     if (rc) return rc;
   }
@@ -1026,6 +1092,8 @@ int clf_query(clf_ctx* c, int what, double* value) {
     }
     case CLF_Q_TILES: *value = c->ntiles; break;
     case CLF_Q_SEGMENT: *value = c->seg; break;
+    case CLF_Q_BLOCKS: *value = eff_blocks(c->nblocks, c->p.persistent_blocks); break;
+    case CLF_Q_GRAPH_REPLAYS: *value = (double)c->graph_replays; break;
     default: return fail(c, CLF_EINVAL, "unknown query %d", what);
   }
   return CLF_OK;
@@ -1038,7 +1106,347 @@ const char* clf_last_error(const clf_ctx* c) {
 int clf_destroy(clf_ctx* c) {
   if (!c) return CLF_EINVAL;
   (void)hipStreamSynchronize(c->stream);
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
+  return CLF_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Ensemble of grids: member contexts in one workspace, one combined
+// descriptor table and tile list, one step-kernel launch per time step.
+// ===========================================================================
+struct clf_ens {
+  hipStream_t stream = nullptr;
+  clf_params p{};
+  int fp32 = 0;
+  int gflags = 0;  // union of the members' flags (kernel variant)
+  std::vector<clf_ctx*> m;
+  GridDesc* gd_dev = nullptr;
+  StepState* st_dev = nullptr;
+  Tile* tiles_dev = nullptr;
+  int tiles_cap = 0;
+  int ntiles = 0, nblocks = 0, seg = 0;
+  long long n = 0;
+  int cur = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  long long graph_replays = 0;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_ens_error;
+
+int efail(clf_ens* e, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (e) e->err = buf;
+  else g_ens_error = buf;
+  return code;
+}
+
+#define EHIPCHK(ens, call)                                                                      \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess) return efail(ens, CLF_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+clf_params member_params(const clf_params& p) {
+  clf_params q = p;
+  q.max_gauges = 0;
+  q.gauge_capacity = 0;
+  q.max_enclosed = 0;
+  q.max_enclosed_points = 0;
+  q.series_capacity = 0;
+  q.forcing_capacity = 0;
+  q.autotune = 0;
+  return q;
+}
+
+struct EnsPlan {
+  size_t gd, st, tiles, total;
+  int tiles_cap;
+  std::vector<size_t> off, size;
+};
+
+EnsPlan ens_plan(int n, const clf_grid* grids, const clf_params& p) {
+  EnsPlan E;
+  const clf_params q = member_params(p);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  E.gd = take(sizeof(GridDesc) * (size_t)n);
+  E.st = take(sizeof(StepState));
+  long long cap = 8LL * WAVES_PER_BLOCK * 2;
+  for (int i = 0; i < n; ++i)
+    cap += (long long)strips_of(grids[i].nx) * ((grids[i].ny + kMinSeg - 1) / kMinSeg);
+  E.tiles_cap = (int)cap;
+  E.tiles = take(sizeof(Tile) * (size_t)cap);
+  for (int i = 0; i < n; ++i) {
+    const size_t sz = plan(grids[i].nx, grids[i].ny, q).total;
+    E.off.push_back(take(sz));
+    E.size.push_back(sz);
+  }
+  E.total = o;
+  return E;
+}
+
+int ens_build_tiles(clf_ens* e, int seg) {
+  std::vector<Tile> nat;
+  for (size_t i = 0; i < e->m.size(); ++i) natural_tiles((int)i, e->m[i]->nx, e->m[i]->ny, seg, nat);
+  int nb = 0;
+  std::vector<Tile> t = xcd_order(nat, &nb);
+  if ((int)t.size() > e->tiles_cap) return efail(e, CLF_EINVAL, "segment %d too short", seg);
+  if (e->graph) {
+    (void)hipGraphExecDestroy(e->graph);
+    e->graph = nullptr;
+  }
+  EHIPCHK(e, hipMemcpyAsync(e->tiles_dev, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                            e->stream));
+  EHIPCHK(e, hipStreamSynchronize(e->stream));
+  e->ntiles = (int)t.size();
+  e->nblocks = nb;
+  e->seg = seg;
+  return CLF_OK;
+}
+
+int ens_default_segment(const clf_ens* e) {
+  long long tiles64 = 0;
+  for (auto* c : e->m) tiles64 += (long long)strips_of(c->nx) * ((c->ny + 63) / 64);
+  return tiles64 >= 4096 ? 64 : 32;
+}
+
+int ens_autotune(clf_ens* e, int* best) {
+  const int cands[] = {16, 24, 32, 48, 64, 96, 128};
+  hipEvent_t a, b;
+  EHIPCHK(e, hipEventCreate(&a));
+  EHIPCHK(e, hipEventCreate(&b));
+  float tb = 1e30f;
+  int bs = ens_default_segment(e);
+  for (int round = 0; round < 2; ++round)
+    for (int seg : cands) {
+      int rc = ens_build_tiles(e, seg);
+      if (rc) return rc;
+      const int nb = eff_blocks(e->nblocks, e->p.persistent_blocks);
+      for (int k = 0; k < 8; ++k) {
+        if (k == 2) EHIPCHK(e, hipEventRecord(a, e->stream));
+        EHIPCHK(e, launch_step(e->fp32, ORD_XY, e->gflags, e->gd_dev, e->tiles_dev, e->ntiles,
+                               e->st_dev, e->cur, 1, nb, e->stream));
+        e->cur ^= 1;
+      }
+      EHIPCHK(e, hipEventRecord(b, e->stream));
+      EHIPCHK(e, hipEventSynchronize(b));
+      float ms = 0.f;
+      EHIPCHK(e, hipEventElapsedTime(&ms, a, b));
+      if (round == 1 && ms < tb) {
+        tb = ms;
+        bs = seg;
+      }
+    }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *best = bs;
+  return CLF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int clf_ensemble_workspace_bytes(int n, const clf_grid* grids, const clf_params* p,
+                                 size_t* bytes) {
+  if (n < 1 || !grids || !p || !bytes) return efail(nullptr, CLF_EINVAL, "bad arguments");
+  for (int i = 0; i < n; ++i) {
+    int rc = validate(&grids[i], p, nullptr);
+    if (rc) return rc;
+  }
+  *bytes = ens_plan(n, grids, *p).total;
+  return CLF_OK;
+}
+
+int clf_ensemble_init(clf_ens** out, int n, const clf_grid* grids, const double* const* depths,
+                      const double* dts, const clf_params* p, void* stream, void* ws,
+                      size_t ws_bytes) {
+  if (!out) return efail(nullptr, CLF_EINVAL, "null output");
+  *out = nullptr;
+  if (n < 1 || !grids || !depths || !dts || !p || !ws)
+    return efail(nullptr, CLF_EINVAL, "bad arguments");
+  for (int i = 0; i < n; ++i) {
+    int rc = validate(&grids[i], p, nullptr);
+    if (rc) return efail(nullptr, rc, "member %d: %s", i, g_init_error.c_str());
+    if (grids[i].nx == 1 || grids[i].ny == 1)
+      return efail(nullptr, CLF_EINVAL, "member %d: ensemble members must be 2-D", i);
+  }
+  if (p->sweep_order != CLF_ORDER_XY)
+    return efail(nullptr, CLF_EINVAL, "ensembles use the x-y order");
+  EnsPlan E = ens_plan(n, grids, *p);
+  if (ws_bytes < E.total)
+    return efail(nullptr, CLF_ENOSPACE, "workspace too small: %zu < %zu", ws_bytes, E.total);
+  if (((uintptr_t)ws) % 256 != 0) return efail(nullptr, CLF_EINVAL, "workspace not aligned");
+  clf_ens* e = new clf_ens();
+  e->stream = (hipStream_t)stream;
+  e->p = *p;
+  e->fp32 = p->precision == CLF_FP32;
+  char* b = (char*)ws;
+  e->gd_dev = (GridDesc*)(b + E.gd);
+  e->st_dev = (StepState*)(b + E.st);
+  e->tiles_dev = (Tile*)(b + E.tiles);
+  e->tiles_cap = E.tiles_cap;
+  const clf_params q = member_params(*p);
+  std::vector<GridDesc> table;
+  for (int i = 0; i < n; ++i) {
+    clf_ctx* c = nullptr;
+    int rc = ctx_create(&c, &grids[i], depths[i], dts[i], &q, stream, b + E.off[i], E.size[i],
+                        false);
+    if (rc) {
+      std::string msg = g_init_error;
+      clf_ensemble_destroy(e);
+      return efail(nullptr, rc, "member %d: %s", i, msg.c_str());
+    }
+    e->m.push_back(c);
+    table.push_back(c->gd);
+    e->gflags |= c->gd.flags;
+  }
+  int rc = CLF_OK;
+  hipError_t he = hipMemcpyAsync(e->gd_dev, table.data(), sizeof(GridDesc) * n,
+                                 hipMemcpyHostToDevice, e->stream);
+  StepState st{};
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(e->st_dev, &st, sizeof st, hipMemcpyHostToDevice, e->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
+  if (he != hipSuccess) rc = efail(e, CLF_EHIP, "upload: %s", hipGetErrorString(he));
+  int seg = p->segment > 0 ? p->segment : ens_default_segment(e);
+  if (rc == CLF_OK) rc = ens_build_tiles(e, seg);
+  if (rc == CLF_OK && p->autotune && p->segment <= 0) {
+    rc = ens_autotune(e, &seg);
+    if (rc == CLF_OK) rc = ens_build_tiles(e, seg);
+    // back to the lake at rest for every member
+    e->cur = 0;
+    for (int i = 0; i < n && rc == CLF_OK; ++i)
+      rc = clf_ensemble_set_initial(e, i, nullptr, nullptr, nullptr, 0);
+  }
+  if (rc != CLF_OK) {
+    std::string msg = e->err;
+    clf_ensemble_destroy(e);
+    return efail(nullptr, rc, "%s", msg.c_str());
+  }
+  *out = e;
+  return CLF_OK;
+}
+
+int clf_ensemble_set_initial(clf_ens* e, int member, const double* eta, const double* u,
+                             const double* v, int deform_bottom) {
+  if (!e) return CLF_EINVAL;
+  if (member < 0 || member >= (int)e->m.size()) return efail(e, CLF_EINVAL, "bad member");
+  clf_ctx* c = e->m[member];
+  const long long N = (long long)c->nx * c->ny;
+  EHIPCHK(e, launch_init_state(e->fp32, &c->gd, c->gd_dev, eta, u, v, deform_bottom ? 1 : 0, N,
+                               e->cur, e->stream));
+  EHIPCHK(e, launch_clear_maxwave(e->fp32, &c->gd, N, e->stream));
+  if (deform_bottom) {
+    // the depth changed on the device; the descriptor (pointers) did not
+  }
+  return CLF_OK;
+}
+
+int clf_ensemble_step(clf_ens* e, int nsteps) {
+  if (!e) return CLF_EINVAL;
+  if (nsteps < 0) return efail(e, CLF_EINVAL, "negative step count");
+  const int nb = eff_blocks(e->nblocks, e->p.persistent_blocks);
+  const bool graphable = e->p.graph_steps > 0 && e->p.maxout == 1;
+  int k = 0;
+  while (k < nsteps) {
+    if (graphable && e->cur == 0 && nsteps - k >= e->p.graph_steps) {
+      if (!e->graph) {
+        clf_ctx tmp;  // error sink for the shared capture helper
+        int rc = build_graph(e->fp32, ORD_XY, e->gflags, e->gd_dev, e->tiles_dev, e->ntiles,
+                             e->st_dev, nb, e->p.graph_steps, &e->cap_stream, &e->graph, &tmp);
+        if (rc) return efail(e, rc, "%s", tmp.err.c_str());
+      }
+      EHIPCHK(e, hipGraphLaunch(e->graph, e->stream));
+      e->graph_replays += 1;
+      e->n += e->p.graph_steps;
+      k += e->p.graph_steps;
+      continue;
+    }
+    const int do_max = ((e->n + 1) % e->p.maxout) == 0;
+    EHIPCHK(e, launch_step(e->fp32, ORD_XY, e->gflags, e->gd_dev, e->tiles_dev, e->ntiles,
+                           e->st_dev, e->cur, do_max, nb, e->stream));
+    e->cur ^= 1;
+    e->n += 1;
+    ++k;
+  }
+  return CLF_OK;
+}
+
+int clf_ensemble_sync(clf_ens* e) {
+  if (!e) return CLF_EINVAL;
+  EHIPCHK(e, hipStreamSynchronize(e->stream));
+  StepState st;
+  EHIPCHK(e, hipMemcpy(&st, e->st_dev, sizeof st, hipMemcpyDeviceToHost));
+  if (st.bad) return efail(e, CLF_ENONFINITE, "state became non-finite");
+  return CLF_OK;
+}
+
+int clf_ensemble_get_state(clf_ens* e, int member, double* eta, double* u, double* v,
+                           uint8_t* wet) {
+  if (!e) return CLF_EINVAL;
+  if (member < 0 || member >= (int)e->m.size()) return efail(e, CLF_EINVAL, "bad member");
+  clf_ctx* c = e->m[member];
+  const long long N = (long long)c->nx * c->ny;
+  EHIPCHK(e, launch_get_state(e->fp32, &c->gd, c->gd_dev, eta, u, v, wet, N, e->cur, e->stream));
+  return clf_ensemble_sync(e);
+}
+
+int clf_ensemble_read_maxwave(clf_ens* e, int member, double* eta_max, double* speed_max) {
+  if (!e) return CLF_EINVAL;
+  if (member < 0 || member >= (int)e->m.size()) return efail(e, CLF_EINVAL, "bad member");
+  clf_ctx* c = e->m[member];
+  const long long N = (long long)c->nx * c->ny;
+  EHIPCHK(e, launch_read_maxwave(e->fp32, &c->gd, c->gd_dev, eta_max, speed_max, N, e->stream));
+  return clf_ensemble_sync(e);
+}
+
+int clf_ensemble_query(clf_ens* e, int what, double* value) {
+  if (!e || !value) return CLF_EINVAL;
+  switch (what) {
+    case CLF_Q_STEP: *value = (double)e->n; break;
+    case CLF_Q_TILES: *value = e->ntiles; break;
+    case CLF_Q_SEGMENT: *value = e->seg; break;
+    case CLF_Q_BLOCKS: *value = eff_blocks(e->nblocks, e->p.persistent_blocks); break;
+    case CLF_Q_GRAPH_REPLAYS: *value = (double)e->graph_replays; break;
+    case CLF_Q_WORKSPACE: {
+      double tot = 0;
+      for (auto* c : e->m) tot += (double)c->L.total;
+      *value = tot;
+      break;
+    }
+    default: return efail(e, CLF_EINVAL, "unknown query %d", what);
+  }
+  return CLF_OK;
+}
+
+const char* clf_ensemble_last_error(const clf_ens* e) {
+  return e ? e->err.c_str() : g_ens_error.c_str();
+}
+
+int clf_ensemble_destroy(clf_ens* e) {
+  if (!e) return CLF_EINVAL;
+  (void)hipStreamSynchronize(e->stream);
+  if (e->graph) (void)hipGraphExecDestroy(e->graph);
+  if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
+  for (auto* c : e->m) clf_destroy(c);
+  delete e;
   return CLF_OK;
 }
 
