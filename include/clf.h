@@ -227,6 +227,32 @@ const char* clf_last_error(const clf_ctx* c);
 int clf_destroy(clf_ctx* c);
 
 /* ------------------------------------------------------------------------
+ * Adjoint (reverse mode) of the FP64 split step, for gradients of a loss of
+ * the gauge records with respect to the initial state (source inversion).
+ * The branch decisions of the wet/dry cycle and of stateh are frozen at the
+ * forward values; the forward run keeps a checkpoint of the state every
+ * ckpt_every steps (default ceil(sqrt(nsteps))) and the reverse run
+ * recomputes each segment from its checkpoint.  Requires an FP64 context,
+ * the x-y order and no boundary forcing; the initial condition must be a
+ * free-surface deformation (deform_bottom = 0).
+ * ------------------------------------------------------------------------ */
+
+/* Device workspace for an adjoint run of nsteps (caller-owned). */
+int clf_adjoint_workspace_bytes(const clf_ctx* c, int nsteps, int ckpt_every, size_t* bytes);
+
+/* Forward run of nsteps from the state set by clf_set_initial (step 0),
+ * recording gauges as clf_step does and storing checkpoints in ws. */
+int clf_adjoint_forward(clf_ctx* c, int nsteps, int ckpt_every, void* ws, size_t ws_bytes);
+
+/* Reverse run.  rec_adj: host [nrec][ng][3], the derivative of the loss with
+ * respect to every gauge record (eta, u, v) of the forward run (nrec must be
+ * the number of records it took).  Outputs: device [ny][nx] FP64 gradients
+ * with respect to the initial surface deformation eta0 and the initial
+ * velocities u0, v0 (any may be NULL).  Synchronises the stream. */
+int clf_adjoint_backward(clf_ctx* c, const double* rec_adj, int nrec, double* d_eta0,
+                         double* d_u0, double* d_v0);
+
+/* ------------------------------------------------------------------------
  * Ensemble: many independent grids (scenarios) of uneven sizes advanced in
  * lockstep.  Each time step is ONE launch of the step kernel over the
  * concatenated tile list of all members (XCD-aware order, optionally a

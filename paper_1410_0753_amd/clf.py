@@ -35,7 +35,8 @@ EXPORTS = ["clf_default_params", "clf_workspace_bytes", "clf_init", "clf_set_ini
            "clf_ensemble_workspace_bytes", "clf_ensemble_init", "clf_ensemble_set_initial",
            "clf_ensemble_step", "clf_ensemble_get_state", "clf_ensemble_read_maxwave",
            "clf_ensemble_sync", "clf_ensemble_query", "clf_ensemble_last_error",
-           "clf_ensemble_destroy"]
+           "clf_ensemble_destroy", "clf_adjoint_workspace_bytes", "clf_adjoint_forward",
+           "clf_adjoint_backward"]
 
 
 class ClfError(RuntimeError):
@@ -113,6 +114,9 @@ def load(build_if_missing: bool = True):
             "clf_ensemble_query": (i32, [vp, i32, C.POINTER(dbl)]),
             "clf_ensemble_last_error": (C.c_char_p, [vp]),
             "clf_ensemble_destroy": (i32, [vp]),
+            "clf_adjoint_workspace_bytes": (i32, [vp, i32, i32, C.POINTER(C.c_size_t)]),
+            "clf_adjoint_forward": (i32, [vp, i32, i32, vp, C.c_size_t]),
+            "clf_adjoint_backward": (i32, [vp, vp, i32, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -305,6 +309,26 @@ class Solver:
         v = C.c_double(0)
         self._check(load().clf_query(self._h, int(what), C.byref(v)))
         return v.value
+
+    # -- adjoint --
+    def adjoint_forward(self, nsteps, ckpt_every=0):
+        """Forward run of nsteps from clf_set_initial, keeping checkpoints."""
+        nb = C.c_size_t(0)
+        self._check(load().clf_adjoint_workspace_bytes(self._h, int(nsteps), int(ckpt_every),
+                                                       C.byref(nb)))
+        self.adj_workspace = self.torch.empty(int(nb.value), dtype=self.torch.uint8,
+                                              device=self.device)
+        self._check(load().clf_adjoint_forward(self._h, int(nsteps), int(ckpt_every),
+                                               C.c_void_p(self.adj_workspace.data_ptr()),
+                                               nb.value))
+
+    def adjoint_backward(self, rec_adj):
+        """rec_adj [nrec][ng][3] -> (dL/deta0, dL/du0, dL/dv0) device tensors."""
+        r = np.ascontiguousarray(rec_adj, dtype=np.float64)
+        de, du, dv = self._empty(), self._empty(), self._empty()
+        self._check(load().clf_adjoint_backward(self._h, r.ctypes.data_as(C.c_void_p), r.shape[0],
+                                                _dptr(de), _dptr(du), _dptr(dv)))
+        return de, du, dv
 
 
 class Ensemble:

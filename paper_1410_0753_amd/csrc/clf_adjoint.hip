@@ -1,0 +1,434 @@
+// Adjoint (reverse mode) of the FP64 split step, for gradients of a gauge
+// misfit with respect to the initial state.
+//
+// One sweep maps the pre-sweep state of a line to the post-sweep state;
+// with the branch decisions of steps (a), (b), (e) and the clipping of
+// stateh frozen at the forward values, node k's output depends on the inputs
+// at k-3..k+3 (radius 1 where the neighbourhood is wet and nothing floods).
+// The adjoint of a sweep is the transposed Jacobian-vector product
+//     lambda_in[j] = sum_{k=j-3..j+3} (d out_k / d in_j)^T lambda_out[k],
+// gathered per input node j (deterministic, no atomics).  Each 3x3 block
+// d out_k / d in_j (fields h, w, t) is obtained by evaluating node k's
+// update once in a forward-mode dual number carrying the three directions
+// of in_j.  The node update below restates the step of the paper (eqQ,
+// solver2/solver1, stateu/stateh, inundation (a)-(e)) for one node from a
+// window of the pre-sweep state, in the same operation order as the
+// forward kernel, so its real part reproduces the forward decisions.
+
+#include "clf_internal.h"
+
+#include <math.h>
+
+namespace clf {
+namespace {
+
+constexpr double kG = 9.81;
+
+// ---------------------------------------------------------------------------
+// Dual number with three derivative directions.
+// ---------------------------------------------------------------------------
+struct D3 {
+  double v, d0, d1, d2;
+};
+
+__device__ __forceinline__ D3 dc(double v) { return D3{v, 0.0, 0.0, 0.0}; }
+__device__ __forceinline__ D3 operator+(const D3& a, const D3& b) {
+  return D3{a.v + b.v, a.d0 + b.d0, a.d1 + b.d1, a.d2 + b.d2};
+}
+__device__ __forceinline__ D3 operator-(const D3& a, const D3& b) {
+  return D3{a.v - b.v, a.d0 - b.d0, a.d1 - b.d1, a.d2 - b.d2};
+}
+__device__ __forceinline__ D3 operator-(const D3& a) { return D3{-a.v, -a.d0, -a.d1, -a.d2}; }
+__device__ __forceinline__ D3 operator*(const D3& a, const D3& b) {
+  return D3{a.v * b.v, a.d0 * b.v + a.v * b.d0, a.d1 * b.v + a.v * b.d1,
+            a.d2 * b.v + a.v * b.d2};
+}
+__device__ __forceinline__ D3 operator*(double s, const D3& a) {
+  return D3{s * a.v, s * a.d0, s * a.d1, s * a.d2};
+}
+__device__ __forceinline__ D3 operator*(const D3& a, double s) {
+  return D3{a.v * s, a.d0 * s, a.d1 * s, a.d2 * s};
+}
+__device__ __forceinline__ D3 operator/(const D3& a, const D3& b) {
+  const double q = a.v / b.v;
+  const double ib = 1.0 / b.v;
+  return D3{q, (a.d0 - q * b.d0) * ib, (a.d1 - q * b.d1) * ib, (a.d2 - q * b.d2) * ib};
+}
+__device__ __forceinline__ D3 dsqrt(const D3& a) {
+  const double s = sqrt(a.v);
+  const double k = s > 0.0 ? 0.5 / s : 0.0;
+  return D3{s, a.d0 * k, a.d1 * k, a.d2 * k};
+}
+__device__ __forceinline__ D3 dcbrt(const D3& a) {
+  const double s = cbrt(a.v);
+  const double k = s != 0.0 ? 1.0 / (3.0 * s * s) : 0.0;
+  return D3{s, a.d0 * k, a.d1 * k, a.d2 * k};
+}
+
+struct AdjPar {
+  double dt, hdt, dt2, hmin, gn2, inv16g, dwall;
+  int flags;
+};
+
+// Node of a line after step (a)/(b): value and flags.
+struct Nd {
+  D3 H, w, t;
+  double D;
+  int ex;   // exists
+  int wet;  // wet after (a) / after (b)
+  int src;  // flood source after (b): -1, +1, 2 (tie), 0
+};
+
+__device__ __forceinline__ double qv(const D3& x) { return x.v; }
+
+__device__ __forceinline__ D3 qhat(const D3& la, const D3& xa, double Da, const D3& lb,
+                                   const D3& xb, double Db, double inv) {
+  D3 s = lb + la;
+  D3 h = 0.5 * s;
+  D3 dx = xb - xa;
+  D3 m = h * dx;
+  double gd = kG * (Db - Da);
+  return (m - dc(gd)) * inv;
+}
+
+__device__ __forceinline__ D3 qhat_t(const D3& la, const D3& xa, const D3& lb, const D3& xb,
+                                     double inv) {
+  D3 s = lb + la;
+  D3 h = 0.5 * s;
+  D3 dx = xb - xa;
+  return (h * dx) * inv;
+}
+
+__device__ __forceinline__ D3 advance(const AdjPar& p, const D3& xi, const D3& lam, const D3& QL,
+                                      const D3& QR, const D3& Qc, double iS) {
+  D3 a3;
+  if (p.flags & G_SOLVER1) {
+    a3 = xi - p.dt * Qc;
+  } else {
+    a3 = xi - p.hdt * (QL + QR);
+  }
+  D3 b3 = (lam * p.dt2) * (QR - QL);
+  return a3 + b3 * iS;
+}
+
+// Steps (c)+(d) for node C with neighbours L, R (post-(b) views).
+__device__ void update_node(const Nd& L, const Nd& C, const Nd& R, double iL, double iR, double iS,
+                            double tanR, const AdjPar& p, D3& Ho, D3& wo, D3& to) {
+  if (!C.wet) {
+    Ho = dc(0.0); wo = dc(0.0); to = dc(0.0);
+    return;
+  }
+  const bool lr = L.ex && L.wet, rr = R.ex && R.wet;
+  const D3 Lw = lr ? L.w : -C.w, Lt = lr ? L.t : C.t;
+  const double LD = lr ? L.D : C.D;
+  const D3 Rw = rr ? R.w : -C.w, Rt = rr ? R.t : C.t;
+  const double RD = rr ? R.D : C.D;
+  const D3 cC = dsqrt(kG * C.H);
+  const D3 cL = lr ? dsqrt(kG * L.H) : cC;
+  const D3 cR = rr ? dsqrt(kG * R.H) : cC;
+  const D3 xPL = Lw + 2.0 * cL, xPC = C.w + 2.0 * cC, xPR = Rw + 2.0 * cR;
+  const D3 lPL = Lw + cL, lPC = C.w + cC, lPR = Rw + cR;
+  const D3 xML = Lw - 2.0 * cL, xMC = C.w - 2.0 * cC, xMR = Rw - 2.0 * cR;
+  const D3 lML = Lw - cL, lMC = C.w - cC, lMR = Rw - cR;
+  const D3 QPL = qhat(lPL, xPL, LD, lPC, xPC, C.D, iL);
+  const D3 QPR = qhat(lPC, xPC, C.D, lPR, xPR, RD, iR);
+  const D3 QML = qhat(lML, xML, LD, lMC, xMC, C.D, iL);
+  const D3 QMR = qhat(lMC, xMC, C.D, lMR, xMR, RD, iR);
+  const D3 QTL = qhat_t(Lw, Lt, C.w, C.t, iL);
+  const D3 QTR = qhat_t(C.w, C.t, Rw, Rt, iR);
+  D3 QPc = dc(0.0), QMc = dc(0.0), QTc = dc(0.0);
+  if (p.flags & G_SOLVER1) {
+    QPc = qhat(lPL, xPL, LD, lPR, xPR, RD, iS);
+    QMc = qhat(lML, xML, LD, lMR, xMR, RD, iS);
+    QTc = qhat_t(Lw, Lt, Rw, Rt, iS);
+  }
+  D3 Pn = advance(p, xPC, lPC, QPL, QPR, QPc, iS);
+  D3 Mn = advance(p, xMC, lMC, QML, QMR, QMc, iS);
+  D3 Tn = advance(p, C.t, C.w, QTL, QTR, QTc, iS);
+  if (tanR != 0.0) {
+    D3 s3 = ((p.dt * cC) * C.w) * tanR;
+    Pn = Pn + s3;
+    Mn = Mn - s3;
+  }
+  D3 wv = 0.5 * (Pn + Mn);
+  D3 dd = Pn - Mn;
+  if (dd.v < 0.0) dd = dc(0.0);
+  D3 Hv = (dd * dd) * p.inv16g;
+  if (p.flags & G_FRICTION) {
+    D3 sp = dsqrt(C.w * C.w + C.t * C.t);
+    D3 den = C.H * dcbrt(C.H);
+    D3 fr = ((p.dt * p.gn2) * sp) / den;
+    wv = wv / (dc(1.0) + fr);
+  }
+  Ho = Hv; wo = wv; to = Tn;
+}
+
+// Step (b) for node C (post-(a) views in, post-(b) view out).
+__device__ Nd flood_node(const Nd& L, const Nd& C, const Nd& R, const AdjPar& p) {
+  Nd b = C;
+  b.src = 0;
+  const bool blocked = (p.flags & G_WALLMODE) && (C.D < p.dwall);
+  if (!C.ex || C.wet || blocked) return b;
+  bool qL = false, qR = false;
+  double fL = 0.0, fR = 0.0;
+  if (L.ex && L.wet) {
+    fL = (L.H.v - L.D) + C.D;
+    qL = fL > p.hmin;
+  }
+  if (R.ex && R.wet) {
+    fR = (R.H.v - R.D) + C.D;
+    qR = fR > p.hmin;
+  }
+  int s = 0;
+  if (qL && qR) s = (fL > fR) ? -1 : ((fR > fL) ? 1 : 2);
+  else if (qL) s = -1;
+  else if (qR) s = 1;
+  if (s == 0) return b;
+  b.src = s;
+  b.wet = 1;
+  b.H = dc(p.hmin);
+  if (s == 2) {
+    b.w = 0.5 * (L.w + R.w);
+    b.t = 0.5 * (L.t + R.t);
+  } else if (s == -1) {
+    b.w = L.w; b.t = L.t;
+  } else {
+    b.w = R.w; b.t = R.t;
+  }
+  return b;
+}
+
+// Line accessor for one sweep: node index along the line -> memory index,
+// existence, inverse spacings and source factor.
+struct Line {
+  const double* H;
+  const double* W;   // normal velocity field of this sweep
+  const double* T;   // tangential velocity field
+  const double* D;
+  long long base;    // memory index of node 0 of the line
+  long long step;    // memory stride along the line
+  int n;             // nodes on the line
+  const double* ib;  // [n+1]
+  const double* isb; // [n]
+  double fac;        // row factor on the inverse spacings (x-sweep), 1 in y
+  const double* tan; // per node tan(lat)/R or null
+};
+
+__device__ __forceinline__ Nd load_pre(const Line& ln, int k, double hmin) {
+  Nd a;
+  a.src = 0;
+  if (k < 0 || k >= ln.n) {
+    a.ex = 0; a.wet = 0; a.D = 0.0;
+    a.H = dc(0.0); a.w = dc(0.0); a.t = dc(0.0);
+    return a;
+  }
+  const long long m = ln.base + (long long)k * ln.step;
+  a.ex = 1;
+  a.D = ln.D[m];
+  a.H = dc(ln.H[m]);
+  a.w = dc(ln.W[m]);
+  a.t = dc(ln.T[m]);
+  // step (a)
+  a.wet = a.H.v > hmin;
+  if (!a.wet) {
+    a.H = dc(0.0); a.w = dc(0.0); a.t = dc(0.0);
+  }
+  return a;
+}
+
+__device__ __forceinline__ void seed(Nd& a) {
+  // directions of this input node: h, w, t (only while it carries them:
+  // a dry node's values were replaced by constants in step (a))
+  if (a.ex && a.wet) {
+    a.H.d0 = 1.0;
+    a.w.d1 = 1.0;
+    a.t.d2 = 1.0;
+  }
+}
+
+__device__ __forceinline__ double ibk(const Line& ln, int k) { return ln.fac * ln.ib[k]; }
+
+// d(out_k)/d(in_j) for output node k of the line and input node j, general
+// radius-3 form: the window k-3..k+3 of the pre-sweep state is re-evaluated
+// through steps (a)-(e) with in_j seeded.
+__device__ void block_general(const Line& ln, int k, int j, const AdjPar& p, D3& Ho, D3& wo,
+                              D3& to) {
+  Nd a[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    a[i] = load_pre(ln, k - 3 + i, p.hmin);
+    if (k - 3 + i == j) seed(a[i]);
+  }
+  Nd b[7];
+#pragma unroll
+  for (int i = 1; i < 6; ++i) b[i] = flood_node(a[i - 1], a[i], a[i + 1], p);
+  D3 Hn[7], wn[7], tn[7];
+  for (int i = 2; i < 5; ++i) {
+    const int kk = k - 3 + i;
+    if (kk < 0 || kk >= ln.n) {
+      Hn[i] = dc(0.0); wn[i] = dc(0.0); tn[i] = dc(0.0);
+      continue;
+    }
+    const double tr = ln.tan ? ln.tan[kk] : 0.0;
+    update_node(b[i - 1], b[i], b[i + 1], ibk(ln, kk), ibk(ln, kk + 1), ln.fac * ln.isb[kk], tr, p,
+                Hn[i], wn[i], tn[i]);
+  }
+  Ho = Hn[3]; wo = wn[3]; to = tn[3];
+  const int s = b[3].src;
+  if (s == 0) return;
+  if (s == 2) {
+    const D3 m = (Hn[4].v < Hn[2].v) ? Hn[4] : Hn[2];
+    const D3 cap = 0.5 * m;
+    if (Ho.v > cap.v) Ho = cap;
+    return;
+  }
+  const int q = 3 + s;
+  const D3 cap = 0.5 * Hn[q];
+  if (Ho.v > cap.v) Ho = cap;
+  if (s == -1) {
+    if (wo.v > wn[q].v) wo = wn[q];
+  } else {
+    if (wo.v < wn[q].v) wo = wn[q];
+  }
+}
+
+// Radius-1 form where nodes k-1..k+1 are wet or missing (nothing floods):
+// steps (c)+(d) of node k only.
+__device__ void block_local(const Line& ln, int k, int j, const AdjPar& p, D3& Ho, D3& wo,
+                            D3& to) {
+  Nd L = load_pre(ln, k - 1, p.hmin), C = load_pre(ln, k, p.hmin), R = load_pre(ln, k + 1, p.hmin);
+  if (j == k - 1) seed(L);
+  if (j == k) seed(C);
+  if (j == k + 1) seed(R);
+  const double tr = ln.tan ? ln.tan[k] : 0.0;
+  update_node(L, C, R, ibk(ln, k), ibk(ln, k + 1), ln.fac * ln.isb[k], tr, p, Ho, wo, to);
+}
+
+__device__ __forceinline__ bool wet_or_missing(const Line& ln, int k, double hmin) {
+  if (k < 0 || k >= ln.n) return true;
+  return ln.H[ln.base + (long long)k * ln.step] > hmin;
+}
+
+// Adjoint of one sweep for input node j of the line.
+__device__ void adjoint_node(const Line& ln, int j, const AdjPar& p, const double* lH,
+                             const double* lW, const double* lT, double& aH, double& aW,
+                             double& aT) {
+  aH = 0.0; aW = 0.0; aT = 0.0;
+  for (int k = j - 3; k <= j + 3; ++k) {
+    if (k < 0 || k >= ln.n) continue;
+    const bool local = wet_or_missing(ln, k - 1, p.hmin) && wet_or_missing(ln, k, p.hmin) &&
+                       wet_or_missing(ln, k + 1, p.hmin);
+    if (local && (k < j - 1 || k > j + 1)) continue;
+    D3 Ho, wo, to;
+    if (local) block_local(ln, k, j, p, Ho, wo, to);
+    else block_general(ln, k, j, p, Ho, wo, to);
+    const long long m = ln.base + (long long)k * ln.step;
+    const double gH = lH[m], gW = lW[m], gT = lT[m];
+    aH += Ho.d0 * gH + wo.d0 * gW + to.d0 * gT;
+    aW += Ho.d1 * gH + wo.d1 * gW + to.d1 * gT;
+    aT += Ho.d2 * gH + wo.d2 * gW + to.d2 * gT;
+  }
+}
+
+// axis 0: lines are rows (w = u, t = v); axis 1: columns (w = v, t = u).
+// pre: state before the sweep; lam_*: adjoint of the state after it;
+// out_*: adjoint of the state before it.
+__global__ void adjoint_sweep_kernel(GridDesc g, int axis, const double* preH, const double* preU,
+                                     const double* preV, const double* lamH, const double* lamU,
+                                     const double* lamV, double* outH, double* outU,
+                                     double* outV) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int jrow = blockIdx.y;
+  if (i >= g.nx || jrow >= g.ny) return;
+  AdjPar p;
+  p.dt = g.dt; p.hdt = g.hdt; p.dt2 = g.dt2; p.hmin = g.hmin; p.gn2 = g.gn2;
+  p.inv16g = g.inv16g; p.dwall = g.dwall; p.flags = g.flags;
+  Line ln;
+  ln.H = preH;
+  ln.D = (const double*)g.D;
+  const long long me = (long long)jrow * g.nx + i;
+  double aH, aW, aT;
+  if (axis == 0) {
+    ln.W = preU; ln.T = preV;
+    ln.base = (long long)jrow * g.nx;
+    ln.step = 1;
+    ln.n = g.nx;
+    ln.ib = (const double*)g.xib;
+    ln.isb = (const double*)g.xisb;
+    ln.fac = ((const double*)g.xfac)[jrow];
+    ln.tan = nullptr;
+    adjoint_node(ln, i, p, lamH, lamU, lamV, aH, aW, aT);
+    outH[me] = aH; outU[me] = aW; outV[me] = aT;
+  } else {
+    ln.W = preV; ln.T = preU;
+    ln.base = i;
+    ln.step = g.nx;
+    ln.n = g.ny;
+    ln.ib = (const double*)g.yib;
+    ln.isb = (const double*)g.yisb;
+    ln.fac = 1.0;
+    ln.tan = (g.flags & G_SPHSRC) ? (const double*)g.tanR : nullptr;
+    adjoint_node(ln, jrow, p, lamH, lamV, lamU, aH, aW, aT);
+    outH[me] = aH; outV[me] = aW; outU[me] = aT;
+  }
+}
+
+// Record adjoints of one level: lambda += d(record)/d(state)^T dL/drecord.
+// A record is (h - d, u, v) on wet nodes, zeros on dry ones.  One thread
+// walks the gauges in order (duplicate gauge nodes add up deterministically).
+__global__ void inject_kernel(GridDesc g, const double* H, const int* gidx, int ng,
+                              const double* rec_adj, double* lamH, double* lamU, double* lamV) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int q = 0; q < ng; ++q) {
+    const int k = gidx[q];
+    if (!(H[k] > g.hmin)) continue;
+    lamH[k] += rec_adj[3 * q + 0];
+    lamU[k] += rec_adj[3 * q + 1];
+    lamV[k] += rec_adj[3 * q + 2];
+  }
+}
+
+// Adjoint of the initial condition h = max(d + eta, 0) (free-surface
+// deformation) with dry nodes zeroed: pass lambda through on wet nodes.
+__global__ void initial_adjoint_kernel(GridDesc g, const double* H0, const double* lamH,
+                                       const double* lamU, const double* lamV, double* dEta,
+                                       double* dU, double* dV, long long N) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const bool wet = H0[k] > g.hmin;
+  if (dEta) dEta[k] = wet ? lamH[k] : 0.0;
+  if (dU) dU[k] = wet ? lamU[k] : 0.0;
+  if (dV) dV[k] = wet ? lamV[k] : 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_sweep(const GridDesc* gd_host, int axis, const double* preH,
+                                const double* preU, const double* preV, const double* lamH,
+                                const double* lamU, const double* lamV, double* outH,
+                                double* outU, double* outV, hipStream_t s) {
+  const int bs = 128;
+  dim3 grid((gd_host->nx + bs - 1) / bs, gd_host->ny);
+  hipLaunchKernelGGL(adjoint_sweep_kernel, grid, dim3(bs), 0, s, *gd_host, axis, preH, preU, preV,
+                     lamH, lamU, lamV, outH, outU, outV);
+  return hipGetLastError();
+}
+
+hipError_t launch_inject(const GridDesc* gd_host, const double* H, const int* gidx, int ng,
+                         const double* rec_adj, double* lamH, double* lamU, double* lamV,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(inject_kernel, dim3(1), dim3(64), 0, s, *gd_host, H, gidx, ng, rec_adj, lamH,
+                     lamU, lamV);
+  return hipGetLastError();
+}
+
+hipError_t launch_initial_adjoint(const GridDesc* gd_host, const double* H0, const double* lamH,
+                                  const double* lamU, const double* lamV, double* dEta, double* dU,
+                                  double* dV, long long N, hipStream_t s) {
+  const int bs = 256;
+  hipLaunchKernelGGL(initial_adjoint_kernel, dim3((unsigned)((N + bs - 1) / bs)), dim3(bs), 0, s,
+                     *gd_host, H0, lamH, lamU, lamV, dEta, dU, dV, N);
+  return hipGetLastError();
+}
+
+}  // namespace clf

@@ -124,4 +124,15 @@ hipError_t launch_forcing(int fp32, const GridDesc* gd_dev, const ForceDesc* fd_
 hipError_t launch_deform_depth(int fp32, const GridDesc* gd_host, const double* eta, long long N,
                                hipStream_t s);
 
+hipError_t launch_adjoint_sweep(const GridDesc* gd_host, int axis, const double* preH,
+                                const double* preU, const double* preV, const double* lamH,
+                                const double* lamU, const double* lamV, double* outH,
+                                double* outU, double* outV, hipStream_t s);
+hipError_t launch_inject(const GridDesc* gd_host, const double* H, const int* gidx, int ng,
+                         const double* rec_adj, double* lamH, double* lamU, double* lamV,
+                         hipStream_t s);
+hipError_t launch_initial_adjoint(const GridDesc* gd_host, const double* H0, const double* lamH,
+                                  const double* lamU, const double* lamV, double* dEta, double* dU,
+                                  double* dV, long long N, hipStream_t s);
+
 }  // namespace clf

@@ -127,6 +127,10 @@ struct clf_ctx {
   hipStream_t cap_stream = nullptr;   // capture-only stream (never runs work)
   hipGraphExec_t graph = nullptr;     // graph_steps steps starting from buffer 0
   long long graph_replays = 0;
+  // adjoint run (caller-owned workspace)
+  char* adj_ws = nullptr;
+  int adj_N = 0, adj_K = 0, adj_nck = 0;
+  bool adj_ready = false;
   std::string err;
 };
 
@@ -1110,6 +1114,206 @@ int clf_destroy(clf_ctx* c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
   return CLF_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Adjoint driver: forward run with checkpoints, reverse run by segments.
+// Workspace: checkpoints [nck] + segment store pre[K+1], mid[K] + three
+// adjoint states + the record adjoints + 2K sweep descriptors.
+// ===========================================================================
+namespace {
+
+struct AdjLayout {
+  size_t state;  // bytes of one (h, u, v) state
+  size_t ck, pre, mid, lam, rec, desc, total;
+};
+
+AdjLayout adj_plan(const clf_ctx* c, int N, int K, int nck, int nrec_max) {
+  AdjLayout A{};
+  const size_t NN = (size_t)c->nx * c->ny;
+  A.state = align_up(3 * NN * sizeof(double), 256);
+  size_t o = 0;
+  A.ck = o; o += (size_t)nck * A.state;
+  A.pre = o; o += (size_t)(K + 1) * A.state;
+  A.mid = o; o += (size_t)K * A.state;
+  A.lam = o; o += 3 * A.state;
+  A.rec = o; o = align_up(o + sizeof(double) * 3 * (size_t)std::max(c->ngauge, 1) *
+                          (size_t)std::max(nrec_max, 1), 256);
+  A.desc = o; o = align_up(o + sizeof(GridDesc) * 2 * (size_t)K, 256);
+  A.total = o;
+  (void)N;
+  return A;
+}
+
+int adj_K(int N, int ckpt) {
+  if (ckpt > 0) return ckpt;
+  int K = (int)std::ceil(std::sqrt((double)std::max(N, 1)));
+  return std::max(K, 1);
+}
+
+struct St3 {
+  double* H;
+  double* U;
+  double* V;
+};
+
+St3 st3(char* base, size_t off, size_t NN) {
+  double* p = (double*)(base + off);
+  return St3{p, p + NN, p + 2 * NN};
+}
+
+int copy_state(clf_ctx* c, St3 dst, const double* H, const double* U, const double* V) {
+  const size_t b = sizeof(double) * (size_t)c->nx * c->ny;
+  HIPCHK(c, hipMemcpyAsync(dst.H, H, b, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(dst.U, U, b, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(dst.V, V, b, hipMemcpyDeviceToDevice, c->stream));
+  return CLF_OK;
+}
+
+int adj_records(const clf_ctx* c, int N) {
+  return c->ngauge > 0 ? (int)records_between(0, c->p.gout, 0, N) : 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int clf_adjoint_workspace_bytes(const clf_ctx* c, int nsteps, int ckpt_every, size_t* bytes) {
+  if (!c || !bytes || nsteps < 1 || ckpt_every < 0) return CLF_EINVAL;
+  const int K = adj_K(nsteps, ckpt_every);
+  const int nck = (nsteps + K - 1) / K;
+  *bytes = adj_plan(c, nsteps, K, nck, adj_records(c, nsteps)).total;
+  return CLF_OK;
+}
+
+int clf_adjoint_forward(clf_ctx* c, int nsteps, int ckpt_every, void* ws, size_t ws_bytes) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (c->fp32) return fail(c, CLF_EINVAL, "the adjoint needs an FP64 context");
+  if (c->p.sweep_order != CLF_ORDER_XY) return fail(c, CLF_EINVAL, "the adjoint needs the x-y order");
+  if (c->forcing) return fail(c, CLF_EINVAL, "the adjoint does not support boundary forcing");
+  if (c->n != 0 || c->rec0) return fail(c, CLF_ESTATE, "call clf_set_initial before the forward run");
+  if (nsteps < 1 || ckpt_every < 0 || !ws) return fail(c, CLF_EINVAL, "bad adjoint arguments");
+  const int K = adj_K(nsteps, ckpt_every);
+  const int nck = (nsteps + K - 1) / K;
+  AdjLayout A = adj_plan(c, nsteps, K, nck, adj_records(c, nsteps));
+  if (ws_bytes < A.total) return fail(c, CLF_ENOSPACE, "adjoint workspace too small");
+  if (((uintptr_t)ws) % 256 != 0) return fail(c, CLF_EINVAL, "adjoint workspace not aligned");
+  c->adj_ws = (char*)ws;
+  c->adj_N = nsteps;
+  c->adj_K = K;
+  c->adj_nck = nck;
+  c->adj_ready = false;
+  const size_t NN = (size_t)c->nx * c->ny;
+  for (int m = 0; m < nck; ++m) {
+    rc = copy_state(c, st3(c->adj_ws, A.ck + (size_t)m * A.state, NN), (const double*)c->gd.H[c->cur],
+                    (const double*)c->gd.U[c->cur], (const double*)c->gd.V[c->cur]);
+    if (rc) return rc;
+    const int len = std::min(K, nsteps - m * K);
+    rc = clf_step(c, len);
+    if (rc) return rc;
+  }
+  // sweep descriptors of the segment store: x maps pre[i] -> mid[i] and y
+  // maps mid[i] -> pre[i+1]; a 1-D grid maps pre[i] -> pre[i+1] directly
+  std::vector<GridDesc> desc(2 * (size_t)K, c->gd);
+  const bool two = c->nx > 1 && c->ny > 1;
+  for (int i = 0; i < K; ++i) {
+    St3 a = st3(c->adj_ws, A.pre + (size_t)i * A.state, NN);
+    St3 b = st3(c->adj_ws, A.mid + (size_t)i * A.state, NN);
+    St3 n1 = st3(c->adj_ws, A.pre + (size_t)(i + 1) * A.state, NN);
+    GridDesc& dx = desc[2 * (size_t)i];
+    GridDesc& dy = desc[2 * (size_t)i + 1];
+    const St3 xo = two ? b : n1;
+    dx.H[0] = a.H; dx.U[0] = a.U; dx.V[0] = a.V;
+    dx.H[1] = xo.H; dx.U[1] = xo.U; dx.V[1] = xo.V;
+    dy.H[0] = b.H; dy.U[0] = b.U; dy.V[0] = b.V;
+    dy.H[1] = n1.H; dy.U[1] = n1.U; dy.V[1] = n1.V;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->adj_ws + A.desc, desc.data(), sizeof(GridDesc) * desc.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  rc = sync_and_check(c);
+  if (rc) return rc;
+  c->adj_ready = true;
+  return CLF_OK;
+}
+
+int clf_adjoint_backward(clf_ctx* c, const double* rec_adj, int nrec, double* d_eta0,
+                         double* d_u0, double* d_v0) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!c->adj_ready) return fail(c, CLF_ESTATE, "no adjoint forward run to reverse");
+  const int N = c->adj_N, K = c->adj_K, nck = c->adj_nck;
+  if (c->n != N) return fail(c, CLF_ESTATE, "the state moved since the adjoint forward run");
+  const int nrec_expect = adj_records(c, N);
+  if (nrec != nrec_expect)
+    return fail(c, CLF_EINVAL, "expected %d gauge records, got %d", nrec_expect, nrec);
+  if (nrec > 0 && !rec_adj) return fail(c, CLF_EINVAL, "null record adjoints");
+  AdjLayout A = adj_plan(c, N, K, nck, nrec_expect);
+  const size_t NN = (size_t)c->nx * c->ny;
+  const size_t fb = sizeof(double) * NN;
+  char* w = c->adj_ws;
+  double* rdev = (double*)(w + A.rec);
+  if (nrec > 0)
+    HIPCHK(c, hipMemcpyAsync(rdev, rec_adj, sizeof(double) * 3 * c->ngauge * (size_t)nrec,
+                             hipMemcpyHostToDevice, c->stream));
+  St3 lam[3] = {st3(w, A.lam, NN), st3(w, A.lam + A.state, NN), st3(w, A.lam + 2 * A.state, NN)};
+  int L = 0;  // index of the current adjoint state (the others are overwritten)
+  HIPCHK(c, hipMemsetAsync(lam[L].H, 0, 3 * fb, c->stream));
+  auto inject = [&](long long level, const double* H) -> int {
+    if (c->ngauge == 0 || level % c->p.gout != 0) return CLF_OK;
+    const long long r = level / c->p.gout;
+    HIPCHK(c, launch_inject(&c->gd, H, c->sd.gidx, c->ngauge, rdev + (size_t)3 * c->ngauge * r,
+                            lam[L].H, lam[L].U, lam[L].V, c->stream));
+    return CLF_OK;
+  };
+  rc = inject(N, (const double*)c->gd.H[c->cur]);
+  if (rc) return rc;
+  const bool two = c->nx > 1 && c->ny > 1;
+  const int axis1 = c->ny == 1 ? 0 : 1;  // the only sweep of a 1-D grid
+  const GridDesc* dtab = (const GridDesc*)(w + A.desc);
+  for (int m = nck - 1; m >= 0; --m) {
+    const int start = m * K;
+    const int len = std::min(K, N - start);
+    St3 ck = st3(w, A.ck + (size_t)m * A.state, NN);
+    St3 p0 = st3(w, A.pre, NN);
+    HIPCHK(c, hipMemcpyAsync(p0.H, ck.H, 3 * fb, hipMemcpyDeviceToDevice, c->stream));
+    for (int i = 0; i < len; ++i) {
+      if (two) {
+        HIPCHK(c, launch_step(0, ORD_X, c->gd.flags, dtab + 2 * i, c->tiles_dev, c->ntiles,
+                              c->st_dev, 0, 0, c->nblocks, c->stream));
+        HIPCHK(c, launch_step(0, ORD_Y, c->gd.flags, dtab + 2 * i + 1, c->tiles_dev, c->ntiles,
+                              c->st_dev, 0, 0, c->nblocks, c->stream));
+      } else {
+        HIPCHK(c, launch_step(0, axis1 == 0 ? ORD_X : ORD_Y, c->gd.flags, dtab + 2 * i,
+                              c->tiles_dev, c->ntiles, c->st_dev, 0, 0, c->nblocks, c->stream));
+      }
+    }
+    for (int i = len - 1; i >= 0; --i) {
+      St3 pre = st3(w, A.pre + (size_t)i * A.state, NN);
+      if (two) {
+        St3 mid = st3(w, A.mid + (size_t)i * A.state, NN);
+        const int Mu = (L + 1) % 3, Nx = (L + 2) % 3;
+        HIPCHK(c, launch_adjoint_sweep(&c->gd, 1, mid.H, mid.U, mid.V, lam[L].H, lam[L].U,
+                                       lam[L].V, lam[Mu].H, lam[Mu].U, lam[Mu].V, c->stream));
+        HIPCHK(c, launch_adjoint_sweep(&c->gd, 0, pre.H, pre.U, pre.V, lam[Mu].H, lam[Mu].U,
+                                       lam[Mu].V, lam[Nx].H, lam[Nx].U, lam[Nx].V, c->stream));
+        L = Nx;
+      } else {
+        const int Nx = (L + 1) % 3;
+        HIPCHK(c, launch_adjoint_sweep(&c->gd, axis1, pre.H, pre.U, pre.V, lam[L].H, lam[L].U,
+                                       lam[L].V, lam[Nx].H, lam[Nx].U, lam[Nx].V, c->stream));
+        L = Nx;
+      }
+      rc = inject(start + i, pre.H);
+      if (rc) return rc;
+    }
+  }
+  St3 s0 = st3(w, A.ck, NN);
+  HIPCHK(c, launch_initial_adjoint(&c->gd, s0.H, lam[L].H, lam[L].U, lam[L].V, d_eta0, d_u0,
+                                   d_v0, (long long)NN, c->stream));
+  return sync_and_check(c);
 }
 
 }  // extern "C"

@@ -1,0 +1,33 @@
+"""Differentiable gauge records for source inversion.
+
+``GaugeRecords.apply(eta0, solver, nsteps, ckpt_every)`` runs the split step
+from the initial surface eta0 (a free-surface deformation) and returns the
+gauge records [nrec][ng][3] (eta, u, v) as a tensor.  Its backward pass is the
+library's adjoint (clf_adjoint_backward): frozen wet/dry decisions, a
+checkpoint every ckpt_every steps (0: ceil(sqrt(nsteps))).  The map from
+source coefficients to eta0 is ordinary torch (a linear combination of unit
+sources), so autograd chains it with the adjoint.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class GaugeRecords(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, eta0, solver, nsteps, ckpt_every=0):
+        solver.set_initial(eta0.detach())
+        solver.adjoint_forward(int(nsteps), int(ckpt_every))
+        rec, _ = solver.read_gauges()
+        ctx.solver = solver
+        return torch.from_numpy(rec).to(device=eta0.device, dtype=eta0.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_rec):
+        d_eta0, _, _ = ctx.solver.adjoint_backward(grad_rec.detach().double().cpu().numpy())
+        return d_eta0, None, None, None
+
+
+def unit_sources_to_eta(coeffs, basis):
+    """eta0 = sum_k c_k G_k (basis [K, ny, nx])."""
+    return torch.tensordot(coeffs, basis, dims=1)

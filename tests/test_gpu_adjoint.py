@@ -1,0 +1,115 @@
+"""Adjoint of the FP64 split step.
+
+Pins: (1) the dot-product identity against the oracle's complex-step
+derivative (frozen branches, machine precision) on a grid with land and
+active wet/dry and on a fully wet grid; (2) central finite differences of the
+GPU forward on a fully wet grid (1e-6 relative); (3) the gradient does not
+depend on the checkpoint interval (bitwise)."""
+import numpy as np
+import pytest
+
+from paper_1410_0753_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def clf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1410_0753_amd import clf as m
+    m.load()
+    return m
+
+
+def misfit_grad(s, eta0, nsteps, obs, ckpt=0):
+    s.set_initial(eta0)
+    s.adjoint_forward(nsteps, ckpt)
+    rec, _ = s.read_gauges()
+    res = rec[:, :, 0] - obs
+    L = 0.5 * np.sum(res ** 2)
+    adj = np.zeros_like(rec)
+    adj[:, :, 0] = res
+    g = s.adjoint_backward(adj)[0].cpu().numpy()
+    return L, g
+
+
+@pytest.mark.parametrize("land", [False, True], ids=["wet", "land"])
+def test_adjoint_dot_product_vs_complex_step(clf, oracle_mod, land):
+    c = synth.random_small(50 + int(land), 70, 52, land=land, amp=0.3)
+    nsteps = 40
+    gx = np.array([5, 30, 60, 44]); gy = np.array([10, 25, 40, 7])
+    s = clf.Solver.from_case(c, gout=2)
+    s.set_gauges(gx, gy)
+    o = oracle_mod.Oracle.from_case(c, gout=2)
+    o.set_gauges(gx, gy)
+    nrec = nsteps // 2 + 1
+    obs = 0.05 * np.random.default_rng(3).standard_normal((nrec, len(gx)))
+    L, g = misfit_grad(s, c.eta0, nsteps, obs)
+    rng = np.random.default_rng(9)
+    for trial in range(3):
+        d = rng.standard_normal(c.eta0.shape) * (c.depth > 0)
+        Lo, dL = o.cs_gauge_loss(c.eta0, d, nsteps, obs)
+        assert abs(Lo - L) <= 1e-12 * abs(L)
+        ad = float(np.sum(g * d))
+        print("land" if land else "wet", trial, ad, dL)
+        assert abs(ad - dL) <= 1e-9 * max(abs(dL), 1e-30) + 1e-14
+
+
+def test_adjoint_vs_finite_differences(clf):
+    case, basis, c_true, c0 = synth.config4(nx=120, ny=96, steps=200, nsrc=6, ngauge=8)
+    nsteps = 200
+    s = clf.Solver.from_case(case, gout=1)
+    s.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
+    eta = lambda c: np.tensordot(c, basis, axes=1)
+    s.set_initial(eta(c_true))
+    s.step(nsteps)
+    obs = s.read_gauges()[0][:, :, 0].copy()
+
+    def loss(c):
+        s.set_initial(eta(c))
+        s.step(nsteps)
+        rec = s.read_gauges()[0][:, :, 0]
+        return 0.5 * np.sum((rec - obs) ** 2)
+
+    L, g_eta = misfit_grad(s, eta(c0), nsteps, obs)
+    g = np.tensordot(basis, g_eta, axes=([1, 2], [0, 1]))
+    h = 1e-4
+    for k in range(len(c0)):
+        e = np.zeros_like(c0); e[k] = h
+        fd = (loss(c0 + e) - loss(c0 - e)) / (2 * h)
+        print(k, g[k], fd)
+        assert abs(g[k] - fd) <= 1e-6 * max(abs(fd), np.abs(g).max())
+
+
+def test_checkpoint_interval_independent(clf):
+    c = synth.random_small(60, 64, 48, land=True, amp=0.3)
+    nsteps = 30
+    gx = np.array([5, 30, 50]); gy = np.array([10, 25, 40])
+    obs = np.zeros((nsteps + 1, 3))
+    out = []
+    for ck in (1, 7, 30, 0):
+        s = clf.Solver.from_case(c, gout=1)
+        s.set_gauges(gx, gy)
+        out.append(misfit_grad(s, c.eta0, nsteps, obs, ckpt=ck)[1])
+    for g in out[1:]:
+        assert np.array_equal(g, out[0])
+
+
+def test_autograd_function(clf):
+    import torch
+    from paper_1410_0753_amd.inversion import GaugeRecords, unit_sources_to_eta
+    case, basis, c_true, c0 = synth.config4(nx=90, ny=72, steps=100, nsrc=4, ngauge=6)
+    s = clf.Solver.from_case(case, gout=1)
+    s.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
+    B = torch.tensor(basis, device="cuda")
+    c = torch.tensor(c0, device="cuda", requires_grad=True)
+    rec = GaugeRecords.apply(unit_sources_to_eta(c, B), s, 100, 0)
+    loss = 0.5 * (rec[:, :, 0] ** 2).sum()
+    loss.backward()
+    assert c.grad is not None and torch.isfinite(c.grad).all()
+    # same as the direct adjoint call
+    L, g_eta = misfit_grad(s, np.tensordot(c0, basis, axes=1), 100, 0.0)
+    g = np.tensordot(basis, g_eta, axes=([1, 2], [0, 1]))
+    assert np.allclose(c.grad.cpu().numpy(), g, rtol=1e-12, atol=0)
