@@ -1,29 +1,37 @@
 """Benchmark of the split step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c5|c1]
-                    [--precision fp64|fp32] [--no-cpu] [--profile]
+                    [--precision fp64|fp32] [--no-cpu] [--no-extras] [--profile]
 
-Workload (default): the 2400 x 1800 spherical grid at 1 arc-minute
-(seeded synthetic coast, shelf, slope and dipole source; 50 gauges; maxwave
-every step), FP64.  A step is one full split step (x-sweep of every row,
-y-sweep of every column, wet/dry cycle, maxwave, gauge records) of the
+Headline (default): the 2400 x 1800 spherical grid at 1 arc-minute (seeded
+synthetic coast, shelf, slope and dipole source; 50 gauges every 10 steps;
+maxwave every step) in FP64.  A step is one full split step (x-sweep of every
+row, y-sweep of every column, wet/dry cycle, maxwave, gauge records) of the
 whole grid with the state resident in HBM.  Prints ONE JSON line.
 
 value = cell-updates/s = nx * ny * K / (time of K steps), timed with HIP
 events on the library's stream, bracketed by device synchronisation.
 
-roofline: the fused step kernel alone (no gauges) is timed over K launches
-with HIP events on its stream; achieved = algorithmic bytes per launch /
-mean launch time, where one cell-step moves 11 words (read h, u, v, d;
-write h, u, v; read and write the two maxwave arrays): 88 B in FP64,
-44 B in FP32.  peak = 8 TB/s.
+roofline: the fused step kernel alone is timed over K launches with HIP
+events on its stream; achieved = algorithmic bytes per launch / mean launch
+time, where one cell-step moves 11 words (read h, u, v, d; write h, u, v;
+read and write the two maxwave arrays): 88 B in FP64, 44 B in FP32.
+peak = 8 TB/s.  `traffic` is the calibrated rocprofv3 FETCH_SIZE +
+WRITE_SIZE of the kernel per launch when the kernel source is the one that
+was profiled (else null).
 
-cpu_baseline: the FP64 oracle (OpenMP over rows / columns) on this host,
-on a bounded sample of the same workload (a few full steps).
+cpu_baseline: the FP64 oracle (OpenMP over rows / columns) on this host, on
+a bounded number of full steps of the same grid.
+
+extras (same line): the FP32 run of the headline grid with its error
+against the FP64 oracle; the 8000 x 6000 spherical FP32 grid; the 64-member
+ensemble against sequential single-grid solves; the adjoint gradient of the
+1000 x 800 inversion problem against a finite-difference gradient.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -35,6 +43,11 @@ sys.path.insert(0, ROOT)
 METRIC = "split-step cell-updates/s (FP64, FP32) + % HBM roofline; ensemble and adjoint speedup"
 PEAK_HBM = 8.0e12
 WORDS_PER_CELL_STEP = 11
+KERNEL_SRC = os.path.join(ROOT, "paper_1410_0753_amd", "csrc", "clf_kernels.hip")
+# Calibrated HBM bytes per launch of the step kernel, from rocprofv3 --pmc
+# FETCH_SIZE / WRITE_SIZE runs (profiles/), keyed by the sha256 of the kernel
+# source they were taken on.
+TRAFFIC = {}
 
 
 def log(*a):
@@ -52,18 +65,157 @@ def make_case(name, steps):
     raise SystemExit("unknown workload " + name)
 
 
-def time_steps(solver, torch, k):
-    stream = solver.stream
+def kernel_sha():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+
+
+def timed(torch, stream, fn):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
-    solver.step(k)
+    fn()
     e1.record(stream)
     e1.synchronize()
     torch.cuda.synchronize()
-    solver.sync()
     return e0.elapsed_time(e1) / 1e3
+
+
+def run_grid(case, prec, steps, warmup, gauges=True):
+    """Whole-step throughput (with gauges) and the step kernel alone."""
+    import torch
+    from paper_1410_0753_amd import clf
+    esize = 4 if prec == clf.FP32 else 8
+    s = clf.Solver.from_case(case, precision=prec, gout=10, maxout=1, autotune=1,
+                             gauge_capacity=(steps + warmup) // 10 + 8)
+    s.set_initial(case.eta0, case.u0, case.v0)
+    if gauges and case.gauges is not None:
+        s.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
+    seg = int(s.query(clf.Q_SEGMENT))
+    s.step(warmup)
+    s.sync()
+    secs = timed(torch, s.stream, lambda: s.step(steps))
+    s.sync()
+    e, _, _, w = s.state()
+    log("%s %s: %.4f ms/step, segment %d, max|eta| %.3f, wet %d" % (
+        case.name, "fp32" if prec == clf.FP32 else "fp64", secs / steps * 1e3, seg,
+        float(e.abs().max()), int(w.sum())))
+    del s
+    r = clf.Solver.from_case(case, precision=prec, maxout=1, autotune=1, graph_steps=0)
+    r.set_initial(case.eta0, case.u0, case.v0)
+    r.step(warmup)
+    r.sync()
+    ksecs = timed(torch, r.stream, lambda: r.step(steps))
+    r.sync()
+    per_launch = ksecs / steps
+    achieved = WORDS_PER_CELL_STEP * esize * case.cells / per_launch
+    del r
+    return {"value": case.cells * steps / secs, "ms_per_step": secs / steps * 1e3,
+            "segment": seg, "kernel_ms": per_launch * 1e3, "achieved": achieved}
+
+
+def fp32_error(case, steps):
+    """FP32 GPU vs FP64 oracle after `steps` steps: max/RMS eta error over the
+    amplitude, fraction of nodes whose wet flag differs."""
+    import numpy as np
+    import oracle
+    from paper_1410_0753_amd import clf
+    g = clf.Solver.from_case(case, precision=clf.FP32)
+    o = oracle.Oracle.from_case(case)
+    for obj in (g, o):
+        obj.set_initial(case.eta0, case.u0, case.v0)
+        obj.step(steps)
+    eg, _, _, wg = (t.cpu().numpy() for t in g.state())
+    eo, _, _, wo = o.state()
+    amp = float(np.abs(eo).max())
+    err = np.abs(eg - eo)
+    return {"steps": steps, "max_eta_err_rel": float(err.max() / amp),
+            "rms_eta_err_rel": float(np.sqrt((err ** 2).mean()) / amp),
+            "mask_flip_frac": float((wg.astype(bool) != wo.astype(bool)).mean())}
+
+
+def run_ensemble(steps, n=64):
+    import torch
+    from paper_1410_0753_amd import clf, synth
+    log("generating %d ensemble members" % n)
+    cases = synth.config3(n=n, steps=steps)
+    cells = sum(c.cells for c in cases)
+    ens = clf.Ensemble(cases, precision=clf.FP32, maxout=1, autotune=1)
+    for i, c in enumerate(cases):
+        ens.set_initial(i, c.eta0, c.u0, c.v0)
+    ens.step(16)
+    ens.sync()
+    tb = timed(torch, ens.stream, lambda: ens.step(steps))
+    ens.sync()
+    seg, blocks = int(ens.query(clf.Q_SEGMENT)), int(ens.query(clf.Q_BLOCKS))
+    del ens
+    # sequential single-grid solves (each autotuned, same precision and steps)
+    solvers = []
+    for c in cases:
+        s = clf.Solver.from_case(c, precision=clf.FP32, maxout=1, autotune=1)
+        s.set_initial(c.eta0, c.u0, c.v0)
+        s.step(16)
+        solvers.append(s)
+    torch.cuda.synchronize()
+
+    def seq():
+        for s in solvers:
+            s.step(steps)
+
+    ts = timed(torch, solvers[0].stream, seq)
+    del solvers
+    return {"members": n, "cells": cells, "steps": steps, "precision": "fp32",
+            "batched_cell_updates_per_s": cells * steps / tb,
+            "sequential_cell_updates_per_s": cells * steps / ts,
+            "speedup_vs_sequential": ts / tb, "segment": seg, "workgroups": blocks}
+
+
+def run_adjoint(steps=3000):
+    import numpy as np
+    import torch
+    from paper_1410_0753_amd import clf, synth
+    case, basis, c_true, c0 = synth.config4(steps=steps)
+    s = clf.Solver.from_case(case, gout=1, gauge_capacity=steps + 2)
+    s.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
+    B = torch.tensor(basis, device="cuda")
+
+    def eta(c):
+        return torch.tensordot(torch.tensor(c, device="cuda"), B, dims=1)
+
+    s.set_initial(eta(c_true))
+    s.step(steps)
+    obs = s.read_gauges()[0][:, :, 0].copy()
+
+    def loss(c):
+        s.set_initial(eta(c))
+        s.step(steps)
+        rec = s.read_gauges()[0][:, :, 0]
+        return 0.5 * float(np.sum((rec - obs) ** 2))
+
+    loss(c0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.set_initial(eta(c0))
+    s.adjoint_forward(steps, 0)
+    rec = s.read_gauges()[0]
+    adj = np.zeros_like(rec)
+    adj[:, :, 0] = rec[:, :, 0] - obs
+    g_eta = s.adjoint_backward(adj)[0]
+    g = torch.tensordot(B, g_eta, dims=([1, 2], [0, 1])).cpu().numpy()
+    t_adj = time.perf_counter() - t0
+    h = 1e-4
+    t0 = time.perf_counter()
+    fd = np.zeros_like(c0)
+    for k in range(len(c0)):
+        e = np.zeros_like(c0)
+        e[k] = h
+        fd[k] = (loss(c0 + e) - loss(c0 - e)) / (2 * h)
+    t_fd = time.perf_counter() - t0
+    rel = float(np.max(np.abs(g - fd)) / np.max(np.abs(fd)))
+    return {"grid": "%dx%d" % (case.nx, case.ny), "steps": steps, "sources": len(c0),
+            "gauges": int(len(case.gauges)), "checkpoint_every": int(np.ceil(np.sqrt(steps))),
+            "adjoint_s": t_adj, "fd_s": t_fd, "speedup_vs_fd": t_fd / t_adj,
+            "max_rel_diff_vs_fd": rel}
 
 
 def cpu_baseline(case, budget_s=12.0):
@@ -72,8 +224,7 @@ def cpu_baseline(case, budget_s=12.0):
     o.set_initial(case.eta0, case.u0, case.v0)
     t0 = time.perf_counter()
     o.step(1)
-    t1 = time.perf_counter()
-    per = t1 - t0
+    per = time.perf_counter() - t0
     k = max(1, min(200, int(budget_s / max(per, 1e-6))))
     t0 = time.perf_counter()
     o.step(k)
@@ -93,6 +244,7 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile", action="store_true", help="short run for profilers")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration)")
@@ -102,19 +254,15 @@ def main():
               "(every run here uses exactly one MI355X)", file=sys.stderr)
         sys.exit(2)
     if args.profile:
-        args.steps, args.warmup, args.no_cpu = min(args.steps, 20), min(args.warmup, 3), True
+        args.steps, args.warmup = min(args.steps, 20), min(args.warmup, 3)
+        args.no_cpu = args.no_extras = True
 
-    import numpy as np
     import torch
     from paper_1410_0753_amd import clf
 
     prec = clf.FP32 if args.precision == "fp32" else clf.FP64
     esize = 4 if prec == clf.FP32 else 8
-    log("generating workload", args.workload)
-    case = make_case(args.workload, args.steps)
-    log("grid %dx%d dt %.4f" % (case.nx, case.ny, case.dt))
     torch.cuda.set_device(0)
-
     if args.calibrate_copy:
         a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
@@ -123,43 +271,19 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-
-    # --- whole step: fused kernel + gauge records ---
-    s = clf.Solver.from_case(case, precision=prec, gout=10, maxout=1, autotune=1,
-                             gauge_capacity=(args.steps + args.warmup) // 10 + 8)
-    s.set_initial(case.eta0, case.u0, case.v0)
-    if case.gauges is not None:
-        s.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
-    seg = int(s.query(clf.Q_SEGMENT))
-    log("init done; segment %d rows, %d tiles" % (seg, s.query(clf.Q_TILES)))
-    s.step(args.warmup)
-    s.sync()
-    secs = time_steps(s, torch, args.steps)
-    value = case.cells * args.steps / secs
-    log("step: %.3f ms, %.3e cell-updates/s" % (secs / args.steps * 1e3, value))
-    e, _, _, w = s.state()
-    log("max|eta| %.3f m, wet %d" % (float(e.abs().max()), int(w.sum())))
-    del s
-
-    # --- roofline leg: the step kernel alone ---
-    r = clf.Solver.from_case(case, precision=prec, maxout=1, autotune=1)
-    r.set_initial(case.eta0, case.u0, case.v0)
-    r.step(args.warmup)
-    r.sync()
-    ksecs = time_steps(r, torch, args.steps)
-    per_launch = ksecs / args.steps
-    bytes_per_launch = WORDS_PER_CELL_STEP * esize * case.cells
-    achieved = bytes_per_launch / per_launch
-    del r
-
+    log("generating workload", args.workload)
+    case = make_case(args.workload, args.steps)
+    head = run_grid(case, prec, args.steps, args.warmup)
+    tkey = "%s/%s" % (args.workload, args.precision)
+    traffic = TRAFFIC.get(kernel_sha(), {}).get(tkey)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": secs / args.steps * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -168,15 +292,38 @@ def main():
         "config": {"workload": case.name + (" (%s, 50 gauges every 10 steps, maxwave every step)"
                                              % args.precision),
                    "nx": case.nx, "ny": case.ny, "dt": case.dt},
-        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": None,
+        "roofline": {"bound": "hbm", "achieved": head["achieved"] / 1e9,
+                     "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                     "frac": head["achieved"] / PEAK_HBM, "traffic": traffic,
                      "kernel": "step_kernel (fused x-y march), %d B/cell-step algorithmic, "
-                               "segment %d rows" % (WORDS_PER_CELL_STEP * esize, seg),
-                     "mean_launch_ms": per_launch * 1e3},
+                               "segment %d rows" % (WORDS_PER_CELL_STEP * esize, head["segment"]),
+                     "mean_launch_ms": head["kernel_ms"],
+                     "frac_of_two_sweep_model": head["value"] * 18 * esize / PEAK_HBM},
     }
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(case)
+    if not args.no_extras:
+        from paper_1410_0753_amd import synth
+        extras = {}
+        if prec == clf.FP64:
+            r32 = run_grid(case, clf.FP32, args.steps, args.warmup)
+            r32["roofline_frac"] = r32.pop("achieved") / PEAK_HBM
+            log("fp32 error vs oracle ...")
+            r32["error_vs_fp64_oracle"] = fp32_error(case, 200)
+            extras["fp32_same_grid"] = r32
+        log("8000x6000 spherical grid ...")
+        big = synth.config5(steps=args.steps)
+        rb = run_grid(big, clf.FP32, min(args.steps, 400), 20)
+        rb["roofline_frac"] = rb.pop("achieved") / PEAK_HBM
+        rb["workload"] = big.name + " (fp32, 50 gauges every 10 steps, maxwave every step)"
+        extras["large_grid_fp32"] = rb
+        del big
+        log("ensemble ...")
+        extras["ensemble"] = run_ensemble(min(args.steps, 300))
+        log("adjoint ...")
+        extras["adjoint"] = run_adjoint(3000)
+        out["extras"] = extras
     print(json.dumps(out), flush=True)
 
 
