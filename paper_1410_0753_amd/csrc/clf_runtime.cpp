@@ -498,7 +498,8 @@ static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c) {
       p->max_enclosed_points < 0 || p->series_capacity < 0 || p->forcing_capacity < 0)
     return fail(c, CLF_EINVAL, "negative capacity");
   if (p->earth_radius <= 0.0) return fail(c, CLF_EINVAL, "earth_radius must be > 0");
-  if (p->segment < 0 || p->segment > 4096) return fail(c, CLF_EINVAL, "segment out of range");
+  if (p->segment != 0 && (p->segment < kMinSeg || p->segment > 4096))
+    return fail(c, CLF_EINVAL, "segment must be 0 (automatic) or in [%d, 4096]", kMinSeg);
   if (p->graph_steps < 0 || (p->graph_steps % 2) != 0 || p->graph_steps > 4096)
     return fail(c, CLF_EINVAL, "graph_steps must be an even number in [0, 4096]");
   if (p->persistent_blocks < 0 || (p->persistent_blocks % 8) != 0)

@@ -368,3 +368,33 @@ def random_small(seed, nx, ny, land=True, amp=0.5, coord=CARTESIAN, dx=100.0):
     depth, eta, u, v = f32(depth), f32(eta), f32(u), f32(v)
     dt = cfl_dt(coord, x, y, np.maximum(depth, 1.0), cfl=0.5)
     return Case("random small %d" % seed, coord, f32(x), f32(y), depth, eta, u, v, dt, 10, 0.1)
+
+
+# --------------------------------------------------------------------------
+# 1-D graded grid: solitary wave on a plane beach (the canonical runup setup
+# of the paper's first example: slope 1:19.85, spacing from d offshore to
+# 0.1 d near the beach, h_min 0.003 m, dt 0.03 s).
+# --------------------------------------------------------------------------
+def beach_1d(H_over_d=0.0185, d=1.0, cot_beta=19.85, land_extent=4.0, steps=2000, dt=0.03):
+    """Returns a 1-D Case (ny = 1).  The sea is at x > 0, the still shoreline
+    at x = 0, land at x < 0; the wave travels toward -x."""
+    toe = cot_beta * d
+    gamma = math.sqrt(3.0 * H_over_d / 4.0) / d
+    half = math.acosh(math.sqrt(20.0)) / gamma
+    x_center = toe + half
+    x_end = x_center + 2.5 * half
+    xs = [-land_extent]
+    while xs[-1] < x_end:
+        xx = xs[-1]
+        frac = min(max(xx / toe, 0.0), 1.0)
+        xs.append(xx + d * (0.1 + 0.9 * frac))
+    x = np.array(xs)
+    depth = np.minimum(d, x / cot_beta)
+    Hw = H_over_d * d
+    eta = Hw / np.cosh(gamma * (x - x_center)) ** 2
+    eta = np.where(depth > 0, eta, 0.0)
+    u = -math.sqrt(G / d) * eta
+    x, depth, eta, u = f32(x), f32(depth)[None, :], f32(eta)[None, :], f32(u)[None, :]
+    return Case("1-D beach H/d=%.4f, %d nodes" % (H_over_d, len(x)), CARTESIAN, x,
+                np.array([0.0]), depth, eta, u, np.zeros_like(u), dt, steps, 0.003,
+                extra={"d": d, "cot_beta": cot_beta, "H": Hw})

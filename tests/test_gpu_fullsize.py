@@ -1,0 +1,89 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (autotuned segment, gauges, maxwave every step), plus randomised tiny
+grids (edge cases: 3-node lines, ragged strips and segments)."""
+import numpy as np
+import pytest
+
+from paper_1410_0753_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def clf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1410_0753_amd import clf as m
+    m.load()
+    return m
+
+
+def test_full_size_2400x1800_fp64_bitwise(clf, oracle_mod):
+    case = synth.config2(steps=20)
+    print("full-size 2400x1800 FP64, 20 steps", flush=True)
+    g = clf.Solver.from_case(case, gout=10, maxout=1, autotune=1)
+    o = oracle_mod.Oracle.from_case(case, gout=10, maxout=1)
+    for obj in (g, o):
+        obj.set_initial(case.eta0, case.u0, case.v0)
+        obj.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
+        obj.step(20)
+    for a, b in zip((t.cpu().numpy() for t in g.raw_state()), o.raw_state()):
+        assert np.array_equal(a, b)
+    assert np.array_equal(g.read_gauges()[0], o.read_gauges()[0])
+    mg = [t.cpu().numpy() for t in g.read_maxwave()]
+    mo = o.read_maxwave()
+    assert np.array_equal(mg[0], mo[0]) and np.array_equal(mg[1], mo[1])
+
+
+def test_full_size_8000x6000_fp32_sampled(clf, oracle_mod):
+    # FP32 on the large grid: error against the FP64 oracle on sampled rows
+    case = synth.config5(steps=4)
+    print("full-size 8000x6000 FP32, 4 steps", flush=True)
+    g = clf.Solver.from_case(case, precision=clf.FP32, autotune=1)
+    g.set_initial(case.eta0)
+    g.step(4)
+    eg, _, _, wg = (t.cpu().numpy() for t in g.state())
+    del g
+    o = oracle_mod.Oracle.from_case(case)
+    o.set_initial(case.eta0)
+    o.step(4)
+    eo, _, _, wo = o.state()
+    rows = np.linspace(0, case.ny - 1, 64).astype(int)
+    amp = np.abs(eo).max()
+    err = np.abs(eg[rows] - eo[rows]).max() / amp
+    flips = (wg[rows] != wo[rows]).mean()
+    print("max eta err %.3e, flips %.3e" % (err, flips))
+    assert err <= 1e-4 and flips <= 1e-4
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_tiny_grids_bitwise(clf, oracle_mod, seed):
+    rng = np.random.default_rng(1000 + seed)
+    nx = int(rng.integers(3, 140))
+    ny = int(rng.integers(3, 90))
+    land = bool(rng.integers(0, 2))
+    case = synth.random_small(seed + 100, nx, ny, land=land, amp=float(rng.uniform(0.05, 1.5)))
+    seg = int(rng.choice([8, 12, 16, 32]))
+    print("seed", seed, nx, ny, land, seg, flush=True)
+    nsteps = int(rng.integers(1, 12))
+    g = clf.Solver.from_case(case, segment=seg)
+    o = oracle_mod.Oracle.from_case(case)
+    for obj in (g, o):
+        obj.set_initial(case.eta0, case.u0, case.v0)
+        obj.step(nsteps)
+    for a, b in zip((t.cpu().numpy() for t in g.raw_state()), o.raw_state()):
+        assert np.array_equal(a, b)
+
+
+def test_zero_steps_and_errors(clf):
+    case = synth.random_small(3, 30, 20)
+    g = clf.Solver.from_case(case)
+    g.set_initial(case.eta0)
+    h0 = g.raw_state()[0].cpu().numpy()
+    g.step(0)
+    assert np.array_equal(g.raw_state()[0].cpu().numpy(), h0)
+    with pytest.raises(clf.ClfError):
+        g.step(-1)
+    with pytest.raises(clf.ClfError):
+        clf.Solver.from_case(case, segment=3)

@@ -696,3 +696,73 @@ def test_mass_defect_converges(oracle_mod):
         defects.append(abs(np.sum(H[0] - d) * dx - vol0) / vol0)
     assert defects[1] < defects[0] and defects[2] < defects[1]
     assert defects[2] <= defects[0] / 3.0
+
+
+# ---------------------------------------------------------------------------
+# Runup of a non-breaking solitary wave on a 1:19.85 beach (the paper's first
+# example, Examples / Runup on a sloping beach) against the published runup
+# law of Synolakis (1987): R/d = 2.831 sqrt(cot beta) (H/d)^(5/4).  Graded
+# 1-D grid (d offshore to 0.1 d near the beach), h_min 0.003 m, dt 0.03 s.
+# ---------------------------------------------------------------------------
+def test_solitary_runup_law(oracle_mod):
+    c = synth.beach_1d(H_over_d=0.0185, steps=1200)
+    o = oracle_mod.Oracle.from_case(c, ssl_alpha=0.0, maxout=1)
+    o.set_initial(c.eta0, c.u0, None)
+    o.step(c.steps)
+    emax, _ = o.read_maxwave()
+    land = c.depth[0] < 0
+    runup = float(emax[0][land].max())
+    law = 2.831 * math.sqrt(19.85) * 0.0185 ** 1.25
+    assert abs(runup / law - 1.0) <= 0.1, (runup, law)
+
+
+# ---------------------------------------------------------------------------
+# Nested-grid chain (Running Options: nested configuration): a parent run
+# records the boundary series of an enclosed grid; the finer child grid,
+# driven by those series on its four sides, reproduces the parent's wave
+# field inside (bilinear parent field as the reference, 10% of the amplitude).
+# ---------------------------------------------------------------------------
+def nested_setup():
+    nxp, nyp, dxp = 150, 120, 400.0
+    xp = np.arange(nxp) * dxp
+    yp = np.arange(nyp) * dxp
+    X, Y = np.meshgrid(xp, yp)
+    dp = 40.0 + 15.0 * np.sin(X / 9000.0) * np.cos(Y / 7000.0)
+    eta = 0.2 * np.exp(-0.5 * (((X - 0.3 * xp[-1]) / 3000.0) ** 2 + ((Y - 0.5 * yp[-1]) / 3000.0) ** 2))
+    xc = xp[60] + np.arange(101) * (dxp / 2)
+    yc = yp[30] + np.arange(121) * (dxp / 2)
+
+    def bilinear(field, xq, yq):
+        i = np.clip(np.searchsorted(xp, xq, side="right") - 1, 0, nxp - 2)
+        j = np.clip(np.searchsorted(yp, yq, side="right") - 1, 0, nyp - 2)
+        wx = (xq - xp[i]) / dxp
+        wy = (yq - yp[j]) / dxp
+        I, J = np.meshgrid(i, j)
+        WX, WY = np.meshgrid(wx, wy)
+        return ((1 - WX) * (1 - WY) * field[J, I] + WX * (1 - WY) * field[J, I + 1]
+                + (1 - WX) * WY * field[J + 1, I] + WX * WY * field[J + 1, I + 1])
+
+    dc = bilinear(dp, xc, yc)
+    dt_p = 0.5 * dxp / np.sqrt(9.81 * 60.0)
+    return dict(xp=xp, yp=yp, dp=dp, eta=eta, xc=xc, yc=yc, dc=dc, dt_p=dt_p, bilinear=bilinear)
+
+
+def test_nested_chain(oracle_mod):
+    S = nested_setup()
+    Np = 120
+    par = oracle_mod.Oracle(S["xp"], S["yp"], S["dp"], S["dt_p"], ssl_alpha=0.0, bndout=1)
+    par.set_initial(S["eta"])
+    gid = par.add_enclosed_grid(S["xc"], S["yc"])
+    par.step(Np)
+    ep = par.state()[0]
+    child = oracle_mod.Oracle(S["xc"], S["yc"], S["dc"], S["dt_p"] / 2, ssl_alpha=0.0)
+    child.set_initial(None)
+    for side in range(4):
+        vals, t = par.read_boundary_series(gid, side)
+        child.set_boundary_forcing(side, t, vals)
+    child.step(2 * Np)
+    ec = child.state()[0]
+    ref = S["bilinear"](ep, S["xc"], S["yc"])
+    amp = np.abs(ref).max()
+    assert amp > 0.01
+    assert np.abs(ec[2:-2, 2:-2] - ref[2:-2, 2:-2]).max() <= 0.1 * amp
