@@ -1,6 +1,7 @@
 """Benchmark of the split step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c5|c1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload c2|c5|c1|ensemble|adjoint]
                     [--precision fp64|fp32] [--no-cpu] [--no-extras] [--profile]
 
 Headline (default): the 2400 x 1800 spherical grid at 1 arc-minute (seeded
@@ -259,6 +260,18 @@ def main():
 
     import torch
     from paper_1410_0753_amd import clf
+
+    if args.workload in ("ensemble", "adjoint"):
+        # one extras leg alone (for profilers)
+        torch.cuda.set_device(0)
+        if args.workload == "ensemble":
+            res = run_ensemble(20 if args.profile else min(args.steps, 300),
+                               n=16 if args.profile else 64)
+        else:
+            res = run_adjoint(200 if args.profile else 3000)
+        print(json.dumps({"metric": METRIC, "workload": args.workload, args.workload: res}),
+              flush=True)
+        return
 
     prec = clf.FP32 if args.precision == "fp32" else clf.FP64
     esize = 4 if prec == clf.FP32 else 8

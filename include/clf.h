@@ -86,7 +86,9 @@ typedef struct clf_ctx clf_ctx;
 /* Grid (Running Options: Bathymetry data; parameter file item 1).
  * x[nx], y[ny] are host arrays, strictly increasing: metres (Cartesian) or
  * decimal degrees (spherical lon/lat).  A 2-D grid needs nx, ny >= 3; a 1-D
- * grid has nx == 1 or ny == 1 and at least 3 nodes along the other axis. */
+ * grid has nx == 1 or ny == 1 and at least 3 nodes along the other axis.
+ * nx * ny must be below 2^32 (the step kernel addresses a grid with 32-bit
+ * element offsets); larger grids are rejected with CLF_EINVAL. */
 typedef struct clf_grid {
   int32_t nx, ny;
   int32_t coord;

@@ -686,7 +686,7 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
     const int xcl = xc < 0 ? 0 : (xc >= nx ? nx - 1 : xc);
     auto load_row = [&](int r, A& a) {
       const int rc = r < 0 ? 0 : (r >= ny ? ny - 1 : r);
-      const long long k = (long long)rc * nx + xcl;
+      const unsigned k = (unsigned)rc * (unsigned)nx + (unsigned)xcl;  // < 2^32 elements
       a.H = gload(cx.H + k);
       a.D = gload(cx.D + k);
       a.w = gload(cx.U + k);   // x view: w = u, t = v
@@ -700,7 +700,7 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
       m.e = 0; m.s2 = 0;
       if (do_max) {
         const int rc = r < 0 ? 0 : (r >= ny ? ny - 1 : r);
-        const long long k = (long long)rc * nx + xcl;
+        const unsigned k = (unsigned)rc * (unsigned)nx + (unsigned)xcl;  // < 2^32 elements
         m.e = gload(cx.emax + k);
         m.s2 = gload(cx.smax2 + k);
       }
@@ -708,7 +708,7 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
     auto store = [&](int r, const C& o, R D, const MW& m) {
       // o in x view: H, w = u, t = v
       if (!out_lane || r < 0 || r >= ny) return;
-      const long long k = (long long)r * nx + xc;
+      const unsigned k = (unsigned)r * (unsigned)nx + (unsigned)xc;
       gstore(cx.Ho + k, o.H);
       gstore(cx.Uo + k, o.w);
       gstore(cx.Vo + k, o.t);

@@ -471,6 +471,8 @@ static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c) {
     return fail(c, CLF_EINVAL, "a 1-D grid needs at least 3 nodes");
   if (!oned && (g->nx < 3 || g->ny < 3))
     return fail(c, CLF_EINVAL, "a 2-D grid needs at least 3 nodes per direction");
+  if ((long long)g->nx * g->ny >= (1LL << 32))
+    return fail(c, CLF_EINVAL, "nx * ny must be below 2^32 (32-bit element offsets)");
   if (g->coord != CLF_CARTESIAN && g->coord != CLF_SPHERICAL)
     return fail(c, CLF_EINVAL, "bad coordinate system");
   if (!g->x || !g->y) return fail(c, CLF_EINVAL, "null coordinates");

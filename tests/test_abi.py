@@ -48,3 +48,20 @@ def test_default_params_and_workspace_size(lib):
     assert n.value >= 9 * 8 * 100 * 50
     bad = clf.Grid(2, 50, 0, g.x, g.y)
     assert lib.clf_workspace_bytes(ctypes.byref(bad), ctypes.byref(p), ctypes.byref(n)) == -1
+
+
+def test_grid_size_limits(lib):
+    # the step kernel uses 32-bit element offsets: nx * ny must stay below 2^32
+    from paper_1410_0753_amd import clf
+    import numpy as np
+    p = clf.Params()
+    lib.clf_default_params(ctypes.byref(p))
+    x = np.arange(65536.0)
+    px = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    n = ctypes.c_size_t(0)
+    lib.clf_workspace_bytes.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    big = clf.Grid(65536, 65536, 0, px, px)
+    assert lib.clf_workspace_bytes(ctypes.byref(big), ctypes.byref(p), ctypes.byref(n)) == -1
+    ok = clf.Grid(65536, 65535, 0, px, px)
+    assert lib.clf_workspace_bytes(ctypes.byref(ok), ctypes.byref(p), ctypes.byref(n)) == 0
+    assert n.value >= 9 * 8 * 65536 * 65535
