@@ -17,15 +17,18 @@ roofline: the fused step kernel alone is timed over K launches with HIP
 events on its stream; achieved = algorithmic bytes per launch / mean launch
 time, where one cell-step moves 11 words (read h, u, v, d; write h, u, v;
 read and write the two maxwave arrays): 88 B in FP64, 44 B in FP32.
-peak = 8 TB/s.  `traffic` is the calibrated rocprofv3 FETCH_SIZE +
-WRITE_SIZE of the kernel per launch when the kernel source is the one that
-was profiled (else null).
+peak = 8 TB/s; copy_GBps is a measured 1 GiB device copy on the same GPU
+(what a plain streaming kernel attains).  `traffic` is the calibrated
+rocprofv3 FETCH_SIZE + WRITE_SIZE of the kernel per launch when the kernel
+source is the one that was profiled (else null).
 
 cpu_baseline: the FP64 oracle (OpenMP over rows / columns) on this host, on
-a bounded number of full steps of the same grid.
+a bounded number of full steps of the same grid, plus a shorter
+single-thread sample.
 
 extras (same line): the FP32 run of the headline grid with its error
-against the FP64 oracle; the 8000 x 6000 spherical FP32 grid; the 64-member
+against the FP64 oracle; the 8000 x 6000 spherical grid (FP32 and FP64, with
+its 4 enclosed-grid boundary series every step); the 64-member
 ensemble against sequential single-grid solves; the adjoint gradient of the
 1000 x 800 inversion problem against a finite-difference gradient.
 """
@@ -82,22 +85,33 @@ def timed(torch, stream, fn):
     return e0.elapsed_time(e1) / 1e3
 
 
-def run_grid(case, prec, steps, warmup, gauges=True):
-    """Whole-step throughput (with gauges) and the step kernel alone."""
+def run_grid(case, prec, steps, warmup, gauges=True, enclosed=False, bndout=1):
+    """Whole-step throughput (with gauges, and the enclosed-grid boundary
+    series every `bndout` steps when `enclosed`) and the step kernel alone."""
     import torch
     from paper_1410_0753_amd import clf
     esize = 4 if prec == clf.FP32 else 8
+    kw = {}
+    if enclosed and case.enclosed:
+        kw = dict(bndout=bndout, max_enclosed=len(case.enclosed),
+                  series_capacity=(steps + warmup) // bndout + 8)
     s = clf.Solver.from_case(case, precision=prec, gout=10, maxout=1, autotune=1,
-                             gauge_capacity=(steps + warmup) // 10 + 8)
+                             gauge_capacity=(steps + warmup) // 10 + 8, **kw)
     s.set_initial(case.eta0, case.u0, case.v0)
     if gauges and case.gauges is not None:
         s.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
+    if kw:
+        for ex, ey in case.enclosed:
+            s.add_enclosed_grid(ex, ey)
+    dry0 = s.state()[3] == 0
     seg = int(s.query(clf.Q_SEGMENT))
     s.step(warmup)
     s.sync()
     secs = timed(torch, s.stream, lambda: s.step(steps))
     s.sync()
     e, _, _, w = s.state()
+    emax = s.read_maxwave()[0]
+    ever_wet = float(((emax > 0) & dry0).sum()) / max(1.0, float(dry0.sum()))
     log("%s %s: %.4f ms/step, segment %d, max|eta| %.3f, wet %d" % (
         case.name, "fp32" if prec == clf.FP32 else "fp64", secs / steps * 1e3, seg,
         float(e.abs().max()), int(w.sum())))
@@ -112,7 +126,23 @@ def run_grid(case, prec, steps, warmup, gauges=True):
     achieved = WORDS_PER_CELL_STEP * esize * case.cells / per_launch
     del r
     return {"value": case.cells * steps / secs, "ms_per_step": secs / steps * 1e3,
-            "segment": seg, "kernel_ms": per_launch * 1e3, "achieved": achieved}
+            "segment": seg, "kernel_ms": per_launch * 1e3, "achieved": achieved,
+            "ever_wet_frac_of_initially_dry": ever_wet,
+            "enclosed_grids": len(case.enclosed) if kw else 0}
+
+
+def copy_bandwidth():
+    """Device-to-device copy of 1 GiB (read + write bytes / time): the
+    attainable HBM rate of a plain streaming kernel on this GPU."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    reps = 10
+    stream = torch.cuda.current_stream()
+    secs = timed(torch, stream, lambda: [b.copy_(a) for _ in range(reps)])
+    del a, b
+    return 2.0 * (1 << 30) * reps / secs
 
 
 def fp32_error(case, steps):
@@ -168,7 +198,8 @@ def run_ensemble(steps, n=64):
     return {"members": n, "cells": cells, "steps": steps, "precision": "fp32",
             "batched_cell_updates_per_s": cells * steps / tb,
             "sequential_cell_updates_per_s": cells * steps / ts,
-            "speedup_vs_sequential": ts / tb, "segment": seg, "workgroups": blocks}
+            "speedup_vs_sequential": ts / tb, "segment": seg, "workgroups": blocks,
+            "roofline_frac": cells * steps / tb * WORDS_PER_CELL_STEP * 4 / PEAK_HBM}
 
 
 def run_adjoint(steps=3000):
@@ -230,11 +261,20 @@ def cpu_baseline(case, budget_s=12.0):
     t0 = time.perf_counter()
     o.step(k)
     t1 = time.perf_counter()
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.set_threads(0)
+    # the same oracle on one thread, a shorter sample
+    oracle.set_threads(1)
+    k1 = max(1, min(k, int(0.25 * budget_s / max(per * threads, 1e-6))))
+    t2 = time.perf_counter()
+    o.step(k1)
+    t3 = time.perf_counter()
+    oracle.set_threads(threads)
     return {"value": case.cells * k / (t1 - t0), "unit": "cell-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": "%d full FP64 split steps of the same %dx%d grid (after 1 warm-up step), "
-                      "%.1f s" % (k, case.nx, case.ny, t1 - t0)}
+                      "%.1f s" % (k, case.nx, case.ny, t1 - t0),
+            "single_thread_value": case.cells * k1 / (t3 - t2),
+            "single_thread_sample": "%d further steps on 1 thread, %.1f s" % (k1, t3 - t2)}
 
 
 def main():
@@ -261,6 +301,15 @@ def main():
     import torch
     from paper_1410_0753_amd import clf
 
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if args.workload in ("ensemble", "adjoint"):
         # one extras leg alone (for profilers)
         torch.cuda.set_device(0)
@@ -275,18 +324,10 @@ def main():
 
     prec = clf.FP32 if args.precision == "fp32" else clf.FP64
     esize = 4 if prec == clf.FP32 else 8
-    torch.cuda.set_device(0)
-    if args.calibrate_copy:
-        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
     log("generating workload", args.workload)
     case = make_case(args.workload, args.steps)
     head = run_grid(case, prec, args.steps, args.warmup)
+    copy_bw = copy_bandwidth()
     tkey = "%s/%s" % (args.workload, args.precision)
     traffic = TRAFFIC.get(kernel_sha(), {}).get(tkey)
     out = {
@@ -311,6 +352,7 @@ def main():
                      "kernel": "step_kernel (fused x-y march), %d B/cell-step algorithmic, "
                                "segment %d rows" % (WORDS_PER_CELL_STEP * esize, head["segment"]),
                      "mean_launch_ms": head["kernel_ms"],
+                     "copy_GBps": copy_bw / 1e9, "frac_of_copy": head["achieved"] / copy_bw,
                      "frac_of_two_sweep_model": head["value"] * 18 * esize / PEAK_HBM},
     }
     if not args.no_cpu:
@@ -327,10 +369,17 @@ def main():
             extras["fp32_same_grid"] = r32
         log("8000x6000 spherical grid ...")
         big = synth.config5(steps=args.steps)
-        rb = run_grid(big, clf.FP32, min(args.steps, 400), 20)
+        rb = run_grid(big, clf.FP32, min(args.steps, 400), 20, enclosed=True)
         rb["roofline_frac"] = rb.pop("achieved") / PEAK_HBM
-        rb["workload"] = big.name + " (fp32, 50 gauges every 10 steps, maxwave every step)"
+        rb["workload"] = big.name + (" (fp32, 50 gauges every 10 steps, maxwave every step, "
+                                     "4 enclosed-grid boundary series every step)")
         extras["large_grid_fp32"] = rb
+        log("8000x6000 spherical grid, fp64 ...")
+        rb = run_grid(big, clf.FP64, min(args.steps, 100), 10, enclosed=True)
+        rb["roofline_frac"] = rb.pop("achieved") / PEAK_HBM
+        rb["workload"] = big.name + (" (fp64, 50 gauges every 10 steps, maxwave every step, "
+                                     "4 enclosed-grid boundary series every step)")
+        extras["large_grid_fp64"] = rb
         del big
         log("ensemble ...")
         extras["ensemble"] = run_ensemble(min(args.steps, 300))

@@ -53,6 +53,7 @@ def lib():
                                      C.c_double, C.c_int, C.c_int, C.c_double, C.c_int,
                                      C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
             L.ora_destroy.argtypes = [C.c_void_p]
+            L.ora_set_threads.argtypes = [C.c_int]
             L.ora_ssl_passes.argtypes = [C.c_void_p]
             L.ora_max_cfl.argtypes = [C.c_void_p]
             L.ora_max_cfl.restype = C.c_double
@@ -94,6 +95,12 @@ def ssl(depth, alpha=2.0, min_depth=0.1):
     ny, nx = d.shape
     passes = lib().ora_ssl(nx, ny, d, alpha, min_depth)
     return d, passes
+
+
+def set_threads(n: int) -> int:
+    """Thread count of the oracle's row / column loops (n <= 0: OpenMP
+    default); returns the count in use.  Results do not depend on it."""
+    return int(lib().ora_set_threads(int(n)))
 
 
 class Oracle:

@@ -47,6 +47,9 @@
 #include <cstdint>
 #include <cstring>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace {
 
@@ -790,6 +793,18 @@ int add_enclosed(Model<double>& m, Enclosed& E, int nxe, int nye, const double* 
 extern "C" {
 
 typedef Model<double> OraModel;
+
+// Thread count of the row / column loops (timing only; results do not
+// depend on it).  n <= 0 leaves the OpenMP default.  Returns the count in use.
+int ora_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
 
 void* ora_create(int nx, int ny, int coord, const double* x, const double* y, const double* depth,
                  double dt, double hmin, double n2, int itopo, double dwall, double ssl_alpha,

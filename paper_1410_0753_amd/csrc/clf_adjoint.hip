@@ -330,10 +330,44 @@ __device__ void adjoint_node(const Line& ln, int j, const AdjPar& p, const doubl
   }
 }
 
+// True when nodes j-4..j+4 of the line are all wet or missing: then every
+// output k = j-3..j+3 has a radius-1 block and only k = j-1..j+1 touch in_j.
+__device__ __forceinline__ bool window_local(const Line& ln, int j, double hmin) {
+  bool ok = true;
+#pragma unroll
+  for (int k = j - 4; k <= j + 4; ++k) ok &= wet_or_missing(ln, k, hmin);
+  return ok;
+}
+
+// Adjoint of one sweep for input node j whose window is local (see above).
+__device__ __forceinline__ void adjoint_node_local(const Line& ln, int j, const AdjPar& p,
+                                                   const double* lH, const double* lW,
+                                                   const double* lT, double& aH, double& aW,
+                                                   double& aT) {
+  aH = 0.0; aW = 0.0; aT = 0.0;
+#pragma unroll
+  for (int k = j - 1; k <= j + 1; ++k) {
+    if (k < 0 || k >= ln.n) continue;
+    D3 Ho, wo, to;
+    block_local(ln, k, j, p, Ho, wo, to);
+    const long long m = ln.base + (long long)k * ln.step;
+    const double gH = lH[m], gW = lW[m], gT = lT[m];
+    aH += Ho.d0 * gH + wo.d0 * gW + to.d0 * gT;
+    aW += Ho.d1 * gH + wo.d1 * gW + to.d1 * gT;
+    aT += Ho.d2 * gH + wo.d2 * gW + to.d2 * gT;
+  }
+}
+
 // axis 0: lines are rows (w = u, t = v); axis 1: columns (w = v, t = u).
 // pre: state before the sweep; lam_*: adjoint of the state after it;
-// out_*: adjoint of the state before it.
-__global__ void adjoint_sweep_kernel(GridDesc g, int axis, const double* preH, const double* preU,
+// out_*: adjoint of the state before it.  The sweep runs as two launches
+// over the same nodes: GENERAL = false takes the nodes whose window is local
+// (the wet interior; small register footprint), GENERAL = true the rest
+// (near the shoreline).  Each node is written by exactly one of them.
+constexpr int kAdjBlock = 128;
+
+template <bool GENERAL>
+__global__ __launch_bounds__(kAdjBlock) void adjoint_sweep_kernel(GridDesc g, int axis, const double* preH, const double* preU,
                                      const double* preV, const double* lamH, const double* lamU,
                                      const double* lamV, double* outH, double* outU,
                                      double* outV) {
@@ -357,7 +391,9 @@ __global__ void adjoint_sweep_kernel(GridDesc g, int axis, const double* preH, c
     ln.isb = (const double*)g.xisb;
     ln.fac = ((const double*)g.xfac)[jrow];
     ln.tan = nullptr;
-    adjoint_node(ln, i, p, lamH, lamU, lamV, aH, aW, aT);
+    if (window_local(ln, i, p.hmin) == GENERAL) return;
+    if (GENERAL) adjoint_node(ln, i, p, lamH, lamU, lamV, aH, aW, aT);
+    else adjoint_node_local(ln, i, p, lamH, lamU, lamV, aH, aW, aT);
     outH[me] = aH; outU[me] = aW; outV[me] = aT;
   } else {
     ln.W = preV; ln.T = preU;
@@ -368,24 +404,33 @@ __global__ void adjoint_sweep_kernel(GridDesc g, int axis, const double* preH, c
     ln.isb = (const double*)g.yisb;
     ln.fac = 1.0;
     ln.tan = (g.flags & G_SPHSRC) ? (const double*)g.tanR : nullptr;
-    adjoint_node(ln, jrow, p, lamH, lamV, lamU, aH, aW, aT);
+    if (window_local(ln, jrow, p.hmin) == GENERAL) return;
+    if (GENERAL) adjoint_node(ln, jrow, p, lamH, lamV, lamU, aH, aW, aT);
+    else adjoint_node_local(ln, jrow, p, lamH, lamV, lamU, aH, aW, aT);
     outH[me] = aH; outV[me] = aW; outU[me] = aT;
   }
 }
 
 // Record adjoints of one level: lambda += d(record)/d(state)^T dL/drecord.
-// A record is (h - d, u, v) on wet nodes, zeros on dry ones.  One thread
-// walks the gauges in order (duplicate gauge nodes add up deterministically).
+// A record is (h - d, u, v) on wet nodes, zeros on dry ones.  One thread per
+// gauge node: the first gauge on a node adds the records of every gauge on
+// that node, in gauge order (deterministic, no atomics).
 __global__ void inject_kernel(GridDesc g, const double* H, const int* gidx, int ng,
                               const double* rec_adj, double* lamH, double* lamU, double* lamV) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  for (int q = 0; q < ng; ++q) {
-    const int k = gidx[q];
-    if (!(H[k] > g.hmin)) continue;
-    lamH[k] += rec_adj[3 * q + 0];
-    lamU[k] += rec_adj[3 * q + 1];
-    lamV[k] += rec_adj[3 * q + 2];
-  }
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ng) return;
+  const int k = gidx[q];
+  for (int r = 0; r < q; ++r)
+    if (gidx[r] == k) return;
+  if (!(H[k] > g.hmin)) return;
+  double aH = lamH[k], aU = lamU[k], aV = lamV[k];
+  for (int r = q; r < ng; ++r)
+    if (gidx[r] == k) {
+      aH += rec_adj[3 * r + 0];
+      aU += rec_adj[3 * r + 1];
+      aV += rec_adj[3 * r + 2];
+    }
+  lamH[k] = aH; lamU[k] = aU; lamV[k] = aV;
 }
 
 // Adjoint of the initial condition h = max(d + eta, 0) (free-surface
@@ -407,18 +452,22 @@ hipError_t launch_adjoint_sweep(const GridDesc* gd_host, int axis, const double*
                                 const double* preU, const double* preV, const double* lamH,
                                 const double* lamU, const double* lamV, double* outH,
                                 double* outU, double* outV, hipStream_t s) {
-  const int bs = 128;
+  const int bs = kAdjBlock;
   dim3 grid((gd_host->nx + bs - 1) / bs, gd_host->ny);
-  hipLaunchKernelGGL(adjoint_sweep_kernel, grid, dim3(bs), 0, s, *gd_host, axis, preH, preU, preV,
-                     lamH, lamU, lamV, outH, outU, outV);
+  hipLaunchKernelGGL(adjoint_sweep_kernel<false>, grid, dim3(bs), 0, s, *gd_host, axis, preH, preU,
+                     preV, lamH, lamU, lamV, outH, outU, outV);
+  hipLaunchKernelGGL(adjoint_sweep_kernel<true>, grid, dim3(bs), 0, s, *gd_host, axis, preH, preU,
+                     preV, lamH, lamU, lamV, outH, outU, outV);
   return hipGetLastError();
 }
 
 hipError_t launch_inject(const GridDesc* gd_host, const double* H, const int* gidx, int ng,
                          const double* rec_adj, double* lamH, double* lamU, double* lamV,
                          hipStream_t s) {
-  hipLaunchKernelGGL(inject_kernel, dim3(1), dim3(64), 0, s, *gd_host, H, gidx, ng, rec_adj, lamH,
-                     lamU, lamV);
+  if (ng <= 0) return hipSuccess;
+  const int bs = 64;
+  hipLaunchKernelGGL(inject_kernel, dim3((ng + bs - 1) / bs), dim3(bs), 0, s, *gd_host, H, gidx, ng,
+                     rec_adj, lamH, lamU, lamV);
   return hipGetLastError();
 }
 

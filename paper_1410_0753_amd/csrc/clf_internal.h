@@ -101,6 +101,8 @@ constexpr int WAVES_PER_BLOCK = 4;
 hipError_t launch_step(int fp32, int order, int gflags, const GridDesc* grids, const Tile* tiles,
                        int ntiles, StepState* st, int parity, int do_max, int nblocks,
                        hipStream_t s);
+// Resident workgroups per compute unit of the step kernel variant.
+hipError_t step_blocks_per_cu(int fp32, int order, int gflags, int* n);
 hipError_t launch_init_state(int fp32, const GridDesc* gd_host, const GridDesc* gd_dev,
                              const double* eta, const double* u, const double* v, int deform,
                              long long N, int parity, hipStream_t s);

@@ -1088,6 +1088,32 @@ hipError_t launch_step(int fp32, int order, int gflags, const GridDesc* grids, c
   return hipGetLastError();
 }
 
+template <class P, int FL>
+static hipError_t occupancy_of(int order, int* n) {
+  const int bs = WAVE * WAVES_PER_BLOCK;
+  switch (order) {
+    case ORD_XY:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          n, reinterpret_cast<const void*>(&step_kernel<P, ORD_XY, FL>), bs, 0);
+    case ORD_YX:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          n, reinterpret_cast<const void*>(&step_kernel<P, ORD_YX, FL>), bs, 0);
+    case ORD_X:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          n, reinterpret_cast<const void*>(&step_kernel<P, ORD_X, FL>), bs, 0);
+    default:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          n, reinterpret_cast<const void*>(&step_kernel<P, ORD_Y, FL>), bs, 0);
+  }
+}
+
+hipError_t step_blocks_per_cu(int fp32, int order, int gflags, int* n) {
+  *n = 0;
+  const bool fast = (gflags & ~FL_FAST) == 0;
+  if (fp32) return fast ? occupancy_of<P32, FL_FAST>(order, n) : occupancy_of<P32, FL_ALL>(order, n);
+  return fast ? occupancy_of<P64, FL_FAST>(order, n) : occupancy_of<P64, FL_ALL>(order, n);
+}
+
 #define CLF_SMALL_LAUNCH(KERNEL, N, ...)                                           \
   do {                                                                             \
     const int bs = 256;                                                            \

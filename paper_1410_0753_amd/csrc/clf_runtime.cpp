@@ -114,6 +114,7 @@ struct clf_ctx {
   ForceDesc* fd_dev = nullptr;
   Tile* tiles_dev = nullptr;
   int ntiles = 0, nblocks = 0, seg = 0;
+  int slots = 0;  // step-kernel workgroups resident per XCD (0: unknown)
   bool have_state = false;
   long long n = 0;
   int cur = 0;
@@ -311,14 +312,70 @@ int build_tiles(clf_ctx* c, int seg) {
   return upload_tiles(c, t, nb, seg);
 }
 
-int default_segment(int nx, int ny) {
-  // enough wavefront tiles to fill 256 CUs several times over, long
-  // segments otherwise (the 6 halo rows of a segment are recomputed)
+// Workgroups that xcd_order gives each XCD for ntiles tiles.
+long long blocks_per_xcd(long long ntiles) {
+  const long long per = (ntiles + kXcds - 1) / kXcds;
+  return (per + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+}
+
+// Step-kernel workgroups resident at once on one XCD (occupancy of the
+// variant times compute units / 8); 0 when unknown.
+int resident_per_xcd(int fp32, int order, int gflags) {
+  int dev = 0, cus = 0, bpc = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (step_blocks_per_cu(fp32, order, gflags, &bpc) != hipSuccess) return 0;
+  return bpc * cus / kXcds;
+}
+
+// Round-aligned segment lengths.  A wave walks its segment plus 6 halo rows
+// at a rate set by latency more than by issue, so a launch takes about
+// (number of workgroup waves) x (segment + 6) row times, and a last, partial
+// wave of workgroups costs a whole one.  For k = 1, 2, ... kmax this returns
+// the shortest segment whose tile list fills at most k full waves of
+// resident workgroups.  tiles(seg) is the tile count for a segment length
+// (non-increasing in seg).
+template <class F>
+std::vector<int> round_segments(F tiles, int slots, int seg_max, int kmax) {
+  std::vector<int> out;
+  if (slots <= 0) return out;
+  seg_max = std::max(seg_max, kMinSeg);
+  for (int k = 1; k <= kmax; ++k) {
+    const long long cap = (long long)k * slots;
+    if (blocks_per_xcd(tiles(seg_max)) > cap) continue;
+    int lo = kMinSeg, hi = seg_max;
+    while (lo < hi) {
+      const int mid = lo + (hi - lo) / 2;
+      if (blocks_per_xcd(tiles(mid)) <= cap) hi = mid;
+      else lo = mid + 1;
+    }
+    if (!out.empty() && out.back() == lo) break;
+    out.push_back(lo);
+    if (lo == kMinSeg) break;
+  }
+  return out;
+}
+
+std::vector<int> grid_round_segments(int nx, int ny, int slots, int kmax) {
+  const long long strips = strips_of(nx);
+  return round_segments([&](int s) { return strips * ((ny + s - 1) / s); }, slots,
+                        std::min(4096, ny), kmax);
+}
+
+int default_segment(int nx, int ny, int slots) {
+  // the fewest full waves of workgroups (one, unless the grid is too large
+  // for 4096-row segments)
+  std::vector<int> r = grid_round_segments(nx, ny, slots, 64);
+  if (!r.empty()) return r.front();
+  // occupancy unknown: enough tiles to fill the GPU several times over
   const long long strips = strips_of(nx);
   int seg = 256;
   while (seg > 16 && strips * ((ny + seg - 1) / seg) < 4096) seg /= 2;
   return seg;
 }
+
+int step_order_of(int nx, int ny) { return ny == 1 ? ORD_X : (nx == 1 ? ORD_Y : ORD_XY); }
 
 // Autotuner: time the step kernel on this grid for candidate segment
 // lengths (rows per wavefront tile) from the lake at rest, keep the fastest.
@@ -336,16 +393,20 @@ int autotune_segment(clf_ctx* c, int* best_seg) {
       return CLF_OK;
     }
   }
-  const int cands[] = {16, 24, 32, 48, 64, 96, 128, 192, 256};
+  // fixed lengths plus the round-aligned ones for up to 4 workgroup waves
+  std::vector<int> cands = {16, 24, 32, 48, 64, 96, 128, 192, 256};
+  for (int sg : grid_round_segments(c->nx, c->ny, c->slots, 4)) cands.push_back(sg);
+  std::sort(cands.begin(), cands.end());
+  cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   float best = 1e30f;
-  int bseg = default_segment(c->nx, c->ny);
-  const int order = c->ny == 1 ? ORD_X : (c->nx == 1 ? ORD_Y : ORD_XY);
+  int bseg = default_segment(c->nx, c->ny, c->slots);
+  const int order = step_order_of(c->nx, c->ny);
   // two rounds over the candidates (the first also warms the clocks); keep
   // each candidate's best time
-  std::vector<float> tbest(sizeof(cands) / sizeof(cands[0]), 1e30f);
+  std::vector<float> tbest(cands.size(), 1e30f);
   for (int round = 0; round < 2; ++round)
     for (size_t ci = 0; ci < tbest.size(); ++ci) {
       const int seg = cands[ci];
@@ -681,7 +742,8 @@ static int ctx_create(clf_ctx** out, const clf_grid* g, const double* depth, dou
     hipError_t e2 = hipMemcpyAsync(c->fd_dev, &c->fd, sizeof c->fd, hipMemcpyHostToDevice, s);
     if (e2 != hipSuccess) r2 = fail(c, CLF_EHIP, "forcing table upload failed");
   }
-  int seg = p->segment > 0 ? p->segment : default_segment(c->nx, c->ny);
+  c->slots = resident_per_xcd(c->fp32, step_order_of(c->nx, c->ny), c->gd.flags);
+  int seg = p->segment > 0 ? p->segment : default_segment(c->nx, c->ny, c->slots);
   if (r2 == CLF_OK && with_tiles) r2 = build_tiles(c, seg);
   if (r2 == CLF_OK) {
     // lake at rest: h = max(d, 0), dry at or below h_min
@@ -1336,6 +1398,7 @@ struct clf_ens {
   Tile* tiles_dev = nullptr;
   int tiles_cap = 0;
   int ntiles = 0, nblocks = 0, seg = 0;
+  int slots = 0;  // step-kernel workgroups resident per XCD (0: unknown)
   long long n = 0;
   int cur = 0;
   hipStream_t cap_stream = nullptr;
@@ -1427,14 +1490,30 @@ int ens_build_tiles(clf_ens* e, int seg) {
   return CLF_OK;
 }
 
+std::vector<int> ens_round_segments(const clf_ens* e, int kmax) {
+  int ny_max = 0;
+  for (auto* c : e->m) ny_max = std::max(ny_max, c->ny);
+  auto tiles = [&](int s) {
+    long long t = 0;
+    for (auto* c : e->m) t += (long long)strips_of(c->nx) * ((c->ny + s - 1) / s);
+    return t;
+  };
+  return round_segments(tiles, e->slots, std::min(4096, ny_max), kmax);
+}
+
 int ens_default_segment(const clf_ens* e) {
+  std::vector<int> r = ens_round_segments(e, 64);
+  if (!r.empty()) return r.front();
   long long tiles64 = 0;
   for (auto* c : e->m) tiles64 += (long long)strips_of(c->nx) * ((c->ny + 63) / 64);
   return tiles64 >= 4096 ? 64 : 32;
 }
 
 int ens_autotune(clf_ens* e, int* best) {
-  const int cands[] = {16, 24, 32, 48, 64, 96, 128};
+  std::vector<int> cands = {16, 24, 32, 48, 64, 96, 128};
+  for (int sg : ens_round_segments(e, 4)) cands.push_back(sg);
+  std::sort(cands.begin(), cands.end());
+  cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
   hipEvent_t a, b;
   EHIPCHK(e, hipEventCreate(&a));
   EHIPCHK(e, hipEventCreate(&b));
@@ -1532,6 +1611,7 @@ int clf_ensemble_init(clf_ens** out, int n, const clf_grid* grids, const double*
     he = hipMemcpyAsync(e->st_dev, &st, sizeof st, hipMemcpyHostToDevice, e->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
   if (he != hipSuccess) rc = efail(e, CLF_EHIP, "upload: %s", hipGetErrorString(he));
+  e->slots = resident_per_xcd(e->fp32, ORD_XY, e->gflags);
   int seg = p->segment > 0 ? p->segment : ens_default_segment(e);
   if (rc == CLF_OK) rc = ens_build_tiles(e, seg);
   if (rc == CLF_OK && p->autotune && p->segment <= 0) {
