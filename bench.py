@@ -327,7 +327,7 @@ def main():
     log("generating workload", args.workload)
     case = make_case(args.workload, args.steps)
     head = run_grid(case, prec, args.steps, args.warmup)
-    copy_bw = copy_bandwidth()
+    copy_bw = None if args.profile else copy_bandwidth()
     tkey = "%s/%s" % (args.workload, args.precision)
     traffic = TRAFFIC.get(kernel_sha(), {}).get(tkey)
     out = {
@@ -352,7 +352,8 @@ def main():
                      "kernel": "step_kernel (fused x-y march), %d B/cell-step algorithmic, "
                                "segment %d rows" % (WORDS_PER_CELL_STEP * esize, head["segment"]),
                      "mean_launch_ms": head["kernel_ms"],
-                     "copy_GBps": copy_bw / 1e9, "frac_of_copy": head["achieved"] / copy_bw,
+                     "copy_GBps": copy_bw / 1e9 if copy_bw else None,
+                     "frac_of_copy": head["achieved"] / copy_bw if copy_bw else None,
                      "frac_of_two_sweep_model": head["value"] * 18 * esize / PEAK_HBM},
     }
     if not args.no_cpu:

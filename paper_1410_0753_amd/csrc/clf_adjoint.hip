@@ -360,30 +360,31 @@ __device__ __forceinline__ void adjoint_node_local(const Line& ln, int j, const 
 
 // axis 0: lines are rows (w = u, t = v); axis 1: columns (w = v, t = u).
 // pre: state before the sweep; lam_*: adjoint of the state after it;
-// out_*: adjoint of the state before it.  The sweep runs as two launches
-// over the same nodes: GENERAL = false takes the nodes whose window is local
-// (the wet interior; small register footprint), GENERAL = true the rest
-// (near the shoreline).  Each node is written by exactly one of them.
+// out_*: adjoint of the state before it.  Node (i, jrow) sits at position
+// i (axis 0) or jrow (axis 1) of its line.
 constexpr int kAdjBlock = 128;
 
-template <bool GENERAL>
-__global__ __launch_bounds__(kAdjBlock) void adjoint_sweep_kernel(GridDesc g, int axis, const double* preH, const double* preU,
-                                     const double* preV, const double* lamH, const double* lamU,
-                                     const double* lamV, double* outH, double* outU,
-                                     double* outV) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int jrow = blockIdx.y;
-  if (i >= g.nx || jrow >= g.ny) return;
+struct SweepArgs {
+  const double *preH, *preU, *preV;
+  const double *lamH, *lamU, *lamV;
+  double *outH, *outU, *outV;
+  unsigned char* flags;  // one per wavefront of the interior launch
+};
+
+__device__ __forceinline__ AdjPar adj_par(const GridDesc& g) {
   AdjPar p;
   p.dt = g.dt; p.hdt = g.hdt; p.dt2 = g.dt2; p.hmin = g.hmin; p.gn2 = g.gn2;
   p.inv16g = g.inv16g; p.dwall = g.dwall; p.flags = g.flags;
+  return p;
+}
+
+template <int AXIS>
+__device__ __forceinline__ Line make_line(const GridDesc& g, const SweepArgs& a, int i, int jrow) {
   Line ln;
-  ln.H = preH;
+  ln.H = a.preH;
   ln.D = (const double*)g.D;
-  const long long me = (long long)jrow * g.nx + i;
-  double aH, aW, aT;
-  if (axis == 0) {
-    ln.W = preU; ln.T = preV;
+  if (AXIS == 0) {
+    ln.W = a.preU; ln.T = a.preV;
     ln.base = (long long)jrow * g.nx;
     ln.step = 1;
     ln.n = g.nx;
@@ -391,12 +392,8 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_sweep_kernel(GridDesc g, in
     ln.isb = (const double*)g.xisb;
     ln.fac = ((const double*)g.xfac)[jrow];
     ln.tan = nullptr;
-    if (window_local(ln, i, p.hmin) == GENERAL) return;
-    if (GENERAL) adjoint_node(ln, i, p, lamH, lamU, lamV, aH, aW, aT);
-    else adjoint_node_local(ln, i, p, lamH, lamU, lamV, aH, aW, aT);
-    outH[me] = aH; outU[me] = aW; outV[me] = aT;
   } else {
-    ln.W = preV; ln.T = preU;
+    ln.W = a.preV; ln.T = a.preU;
     ln.base = i;
     ln.step = g.nx;
     ln.n = g.ny;
@@ -404,10 +401,65 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_sweep_kernel(GridDesc g, in
     ln.isb = (const double*)g.yisb;
     ln.fac = 1.0;
     ln.tan = (g.flags & G_SPHSRC) ? (const double*)g.tanR : nullptr;
-    if (window_local(ln, jrow, p.hmin) == GENERAL) return;
-    if (GENERAL) adjoint_node(ln, jrow, p, lamH, lamV, lamU, aH, aW, aT);
-    else adjoint_node_local(ln, jrow, p, lamH, lamV, lamU, aH, aW, aT);
-    outH[me] = aH; outV[me] = aW; outU[me] = aT;
+  }
+  return ln;
+}
+
+template <int AXIS, bool GENERAL>
+__device__ __forceinline__ void sweep_node(const GridDesc& g, const SweepArgs& a, const Line& ln,
+                                           const AdjPar& p, int i, int jrow) {
+  const long long me = (long long)jrow * g.nx + i;
+  const int j = AXIS == 0 ? i : jrow;
+  // the adjoint's normal / tangential fields follow the sweep axis
+  const double* lW = AXIS == 0 ? a.lamU : a.lamV;
+  const double* lT = AXIS == 0 ? a.lamV : a.lamU;
+  double aH, aW, aT;
+  if (GENERAL) adjoint_node(ln, j, p, a.lamH, lW, lT, aH, aW, aT);
+  else adjoint_node_local(ln, j, p, a.lamH, lW, lT, aH, aW, aT);
+  a.outH[me] = aH;
+  if (AXIS == 0) { a.outU[me] = aW; a.outV[me] = aT; }
+  else { a.outV[me] = aW; a.outU[me] = aT; }
+}
+
+// Interior launch: one thread per node, grid (ceil(nx / kAdjBlock), ny).
+// Nodes whose window is local are done here (small register footprint);
+// a wavefront holding any other node sets its flag for the shoreline launch.
+template <int AXIS>
+__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(3))) void adjoint_local_kernel(GridDesc g, SweepArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int jrow = blockIdx.y;
+  const bool in = i < g.nx;
+  const AdjPar p = adj_par(g);
+  const Line ln = make_line<AXIS>(g, a, in ? i : 0, jrow);
+  const bool local = in && window_local(ln, AXIS == 0 ? i : jrow, p.hmin);
+  const unsigned long long other = __ballot(in && !local);
+  if (other != 0 && (threadIdx.x & 63) == 0) {
+    const int wave = (blockIdx.y * gridDim.x + blockIdx.x) * (kAdjBlock / 64) + threadIdx.x / 64;
+    a.flags[wave] = 1;
+  }
+  if (!local) return;
+  sweep_node<AXIS, false>(g, a, ln, p, i, jrow);
+}
+
+// Shoreline launch: one wavefront per workgroup, grid-stride over the
+// interior launch's wavefronts; a flagged one is redone here for its
+// non-local nodes, and its flag is cleared for the next sweep.
+template <int AXIS>
+__global__ __launch_bounds__(64) void adjoint_general_kernel(GridDesc g, SweepArgs a, int nwaves,
+                                                             int gx) {
+  constexpr int kWpb = kAdjBlock / 64;
+  const AdjPar p = adj_par(g);
+  for (int w = blockIdx.x; w < nwaves; w += gridDim.x) {
+    if (a.flags[w] == 0) continue;
+    const int b = w / kWpb, part = w % kWpb;
+    const int jrow = b / gx;
+    const int i = (b % gx) * kAdjBlock + part * 64 + (int)threadIdx.x;
+    if (i < g.nx) {
+      const Line ln = make_line<AXIS>(g, a, i, jrow);
+      if (!window_local(ln, AXIS == 0 ? i : jrow, p.hmin)) sweep_node<AXIS, true>(g, a, ln, p, i, jrow);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a.flags[w] = 0;
   }
 }
 
@@ -448,16 +500,26 @@ __global__ void initial_adjoint_kernel(GridDesc g, const double* H0, const doubl
 
 }  // namespace
 
+int adjoint_flag_count(int nx, int ny) {
+  return (nx + kAdjBlock - 1) / kAdjBlock * (kAdjBlock / 64) * ny;
+}
+
 hipError_t launch_adjoint_sweep(const GridDesc* gd_host, int axis, const double* preH,
                                 const double* preU, const double* preV, const double* lamH,
                                 const double* lamU, const double* lamV, double* outH,
-                                double* outU, double* outV, hipStream_t s) {
-  const int bs = kAdjBlock;
-  dim3 grid((gd_host->nx + bs - 1) / bs, gd_host->ny);
-  hipLaunchKernelGGL(adjoint_sweep_kernel<false>, grid, dim3(bs), 0, s, *gd_host, axis, preH, preU,
-                     preV, lamH, lamU, lamV, outH, outU, outV);
-  hipLaunchKernelGGL(adjoint_sweep_kernel<true>, grid, dim3(bs), 0, s, *gd_host, axis, preH, preU,
-                     preV, lamH, lamU, lamV, outH, outU, outV);
+                                double* outU, double* outV, unsigned char* flags, hipStream_t s) {
+  SweepArgs a{preH, preU, preV, lamH, lamU, lamV, outH, outU, outV, flags};
+  const int gx = (gd_host->nx + kAdjBlock - 1) / kAdjBlock;
+  const int nwaves = adjoint_flag_count(gd_host->nx, gd_host->ny);
+  const int nb = nwaves < 1024 ? nwaves : 1024;
+  const dim3 grid(gx, gd_host->ny), block(kAdjBlock);
+  if (axis == 0) {
+    hipLaunchKernelGGL(adjoint_local_kernel<0>, grid, block, 0, s, *gd_host, a);
+    hipLaunchKernelGGL(adjoint_general_kernel<0>, dim3(nb), dim3(64), 0, s, *gd_host, a, nwaves, gx);
+  } else {
+    hipLaunchKernelGGL(adjoint_local_kernel<1>, grid, block, 0, s, *gd_host, a);
+    hipLaunchKernelGGL(adjoint_general_kernel<1>, dim3(nb), dim3(64), 0, s, *gd_host, a, nwaves, gx);
+  }
   return hipGetLastError();
 }
 

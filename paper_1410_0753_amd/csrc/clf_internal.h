@@ -126,10 +126,13 @@ hipError_t launch_forcing(int fp32, const GridDesc* gd_dev, const ForceDesc* fd_
 hipError_t launch_deform_depth(int fp32, const GridDesc* gd_host, const double* eta, long long N,
                                hipStream_t s);
 
+// Flags used by the adjoint sweep (bytes; zero them once before the first
+// sweep, every sweep leaves them zero).
+int adjoint_flag_count(int nx, int ny);
 hipError_t launch_adjoint_sweep(const GridDesc* gd_host, int axis, const double* preH,
                                 const double* preU, const double* preV, const double* lamH,
                                 const double* lamU, const double* lamV, double* outH,
-                                double* outU, double* outV, hipStream_t s);
+                                double* outU, double* outV, unsigned char* flags, hipStream_t s);
 hipError_t launch_inject(const GridDesc* gd_host, const double* H, const int* gidx, int ng,
                          const double* rec_adj, double* lamH, double* lamU, double* lamV,
                          hipStream_t s);

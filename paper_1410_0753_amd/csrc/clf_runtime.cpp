@@ -1192,7 +1192,7 @@ namespace {
 
 struct AdjLayout {
   size_t state;  // bytes of one (h, u, v) state
-  size_t ck, pre, mid, lam, rec, desc, total;
+  size_t ck, pre, mid, lam, rec, desc, flags, total;
 };
 
 AdjLayout adj_plan(const clf_ctx* c, int N, int K, int nck, int nrec_max) {
@@ -1207,6 +1207,7 @@ AdjLayout adj_plan(const clf_ctx* c, int N, int K, int nck, int nrec_max) {
   A.rec = o; o = align_up(o + sizeof(double) * 3 * (size_t)std::max(c->ngauge, 1) *
                           (size_t)std::max(nrec_max, 1), 256);
   A.desc = o; o = align_up(o + sizeof(GridDesc) * 2 * (size_t)K, 256);
+  A.flags = o; o = align_up(o + (size_t)adjoint_flag_count(c->nx, c->ny), 256);
   A.total = o;
   (void)N;
   return A;
@@ -1326,6 +1327,8 @@ int clf_adjoint_backward(clf_ctx* c, const double* rec_adj, int nrec, double* d_
   St3 lam[3] = {st3(w, A.lam, NN), st3(w, A.lam + A.state, NN), st3(w, A.lam + 2 * A.state, NN)};
   int L = 0;  // index of the current adjoint state (the others are overwritten)
   HIPCHK(c, hipMemsetAsync(lam[L].H, 0, 3 * fb, c->stream));
+  unsigned char* flags = (unsigned char*)(w + A.flags);
+  HIPCHK(c, hipMemsetAsync(flags, 0, (size_t)adjoint_flag_count(c->nx, c->ny), c->stream));
   auto inject = [&](long long level, const double* H) -> int {
     if (c->ngauge == 0 || level % c->p.gout != 0) return CLF_OK;
     const long long r = level / c->p.gout;
@@ -1361,14 +1364,14 @@ int clf_adjoint_backward(clf_ctx* c, const double* rec_adj, int nrec, double* d_
         St3 mid = st3(w, A.mid + (size_t)i * A.state, NN);
         const int Mu = (L + 1) % 3, Nx = (L + 2) % 3;
         HIPCHK(c, launch_adjoint_sweep(&c->gd, 1, mid.H, mid.U, mid.V, lam[L].H, lam[L].U,
-                                       lam[L].V, lam[Mu].H, lam[Mu].U, lam[Mu].V, c->stream));
+                                       lam[L].V, lam[Mu].H, lam[Mu].U, lam[Mu].V, flags, c->stream));
         HIPCHK(c, launch_adjoint_sweep(&c->gd, 0, pre.H, pre.U, pre.V, lam[Mu].H, lam[Mu].U,
-                                       lam[Mu].V, lam[Nx].H, lam[Nx].U, lam[Nx].V, c->stream));
+                                       lam[Mu].V, lam[Nx].H, lam[Nx].U, lam[Nx].V, flags, c->stream));
         L = Nx;
       } else {
         const int Nx = (L + 1) % 3;
         HIPCHK(c, launch_adjoint_sweep(&c->gd, axis1, pre.H, pre.U, pre.V, lam[L].H, lam[L].U,
-                                       lam[L].V, lam[Nx].H, lam[Nx].U, lam[Nx].V, c->stream));
+                                       lam[L].V, lam[Nx].H, lam[Nx].U, lam[Nx].V, flags, c->stream));
         L = Nx;
       }
       rc = inject(start + i, pre.H);
