@@ -21,7 +21,9 @@ def clf():
 
 
 def test_beach_runup_bitwise(clf, oracle_mod):
-    c = synth.beach_1d(H_over_d=0.0185, steps=1200)
+    from tests.golden import load
+    gb = load("sloping_beach.txt")
+    c = synth.beach_1d(H_over_d=gb["H_over_d"], cot_beta=gb["cot_beta"], steps=1200)
     g = clf.Solver.from_case(c, ssl_alpha=0.0, maxout=1)
     o = oracle_mod.Oracle.from_case(c, ssl_alpha=0.0, maxout=1)
     for obj in (g, o):
@@ -33,7 +35,7 @@ def test_beach_runup_bitwise(clf, oracle_mod):
     for a, b in zip((t.cpu().numpy() for t in g.raw_state()), o.raw_state()):
         assert np.array_equal(a, b)
     land = c.depth[0] < 0
-    law = 2.831 * math.sqrt(19.85) * 0.0185 ** 1.25
+    law = gb["runup_law_coefficient"] * math.sqrt(gb["cot_beta"]) * gb["H_over_d"] ** 1.25
     assert abs(mg[0][land].max() / law - 1.0) <= 0.1
 
 

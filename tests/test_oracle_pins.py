@@ -705,14 +705,16 @@ def test_mass_defect_converges(oracle_mod):
 # 1-D grid (d offshore to 0.1 d near the beach), h_min 0.003 m, dt 0.03 s.
 # ---------------------------------------------------------------------------
 def test_solitary_runup_law(oracle_mod):
-    c = synth.beach_1d(H_over_d=0.0185, steps=1200)
+    from tests.golden import load
+    gb = load("sloping_beach.txt")
+    c = synth.beach_1d(H_over_d=gb["H_over_d"], cot_beta=gb["cot_beta"], steps=1200)
     o = oracle_mod.Oracle.from_case(c, ssl_alpha=0.0, maxout=1)
     o.set_initial(c.eta0, c.u0, None)
     o.step(c.steps)
     emax, _ = o.read_maxwave()
     land = c.depth[0] < 0
     runup = float(emax[0][land].max())
-    law = 2.831 * math.sqrt(19.85) * 0.0185 ** 1.25
+    law = gb["runup_law_coefficient"] * math.sqrt(gb["cot_beta"]) * gb["H_over_d"] ** 1.25
     assert abs(runup / law - 1.0) <= 0.1, (runup, law)
 
 
