@@ -84,8 +84,18 @@ __device__ __forceinline__ void gstore(T* p, T v) {
 // ---------------------------------------------------------------------------
 // FP64 node stages (literal form).
 // ---------------------------------------------------------------------------
+#ifndef CLF_PREFETCH64
+#define CLF_PREFETCH64 2
+#endif
+#ifndef CLF_PREFETCH32
+#define CLF_PREFETCH32 1
+#endif
+
 struct P64 {
   typedef double R;
+  // march rows between a row's load and its use (latency cover for the
+  // 3 waves per SIMD that the FP64 register footprint allows)
+  static constexpr int kPrefetch = CLF_PREFETCH64;
   // post-(a) view of a node along the sweep line: w normal, t tangential
   struct A { double H, w, t, D; int f; int pad; };
   // post-(b) view: c = sqrt(g H) on wet nodes
@@ -306,6 +316,7 @@ struct P64 {
 // ---------------------------------------------------------------------------
 struct P32 {
   typedef float R;
+  static constexpr int kPrefetch = CLF_PREFETCH32;
   static constexpr float kGf = 9.81f;
   struct A { float H, w, t, D; int f; int pad; };          // H = eta
   struct B { float H, w, t, D, c, h; int f; int src; };   // h = total height
@@ -741,15 +752,19 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
       A pf[3];
       MW pm[3];
       const int r_first = tl.y0 - HALO, r_end = tl.y0 + tl.rows + HALO;
+      // rows are loaded PF = P::kPrefetch march rows ahead of use (1 or 2:
+      // the three slots hold the row in use and up to two in flight)
+      constexpr int PF = P::kPrefetch;
       load_row(r_first, pf[0]);
+      if (PF == 2) load_row(r_first + 1, pf[1]);
       load_mw(r_first - HALO, pm[0]);
       // one march row in phase K: consume pf[K] (row r) and pm[K] (maxwave of
-      // the output row r-3); prefetch row r+1 and the maxwave of row r-2
+      // the output row r-3); prefetch row r+PF and the maxwave of row r-2
       auto body = [&](auto phase, int r) {
         constexpr int K = decltype(phase)::value;
         A a = pf[K];
         MW m = pm[K];
-        load_row(r + 1, pf[(K + 1) % 3]);
+        load_row(r + PF, pf[(K + PF) % 3]);
         load_mw(r + 1 - HALO, pm[(K + 1) % 3]);
         if (ORDER == ORD_YX) {
           A ay = a;
