@@ -354,7 +354,11 @@ def main():
                      "mean_launch_ms": head["kernel_ms"],
                      "copy_GBps": copy_bw / 1e9 if copy_bw else None,
                      "frac_of_copy": head["achieved"] / copy_bw if copy_bw else None,
-                     "frac_of_two_sweep_model": head["value"] * 18 * esize / PEAK_HBM},
+                     "frac_of_two_sweep_model": head["value"] * 18 * esize / PEAK_HBM,
+                     "note": "frac uses the fused kernel's 11 words per cell-step; "
+                             "frac_of_two_sweep_model the 18 words of two separate sweeps "
+                             "with maxwave. Grids up to about 2400x1800 FP64 fit the 256 MB "
+                             "Infinity Cache; the HBM-resident runs are the 8000x6000 extras."},
     }
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
