@@ -76,6 +76,14 @@ template <class T>
 __device__ __forceinline__ T gload(const T* p) {
   return *(const __attribute__((address_space(1))) T*)p;
 }
+// Load of read-only data at a wavefront-uniform address (row metrics):
+// through the constant address space the compiler may use a scalar load,
+// which is counted apart from the vector loads, so waiting for it does not
+// also wait for the rows prefetched before it.
+template <class T>
+__device__ __forceinline__ T cload(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)p;
+}
 template <class T>
 __device__ __forceinline__ void gstore(T* p, T v) {
   *(__attribute__((address_space(1))) T*)p = v;
@@ -88,13 +96,12 @@ __device__ __forceinline__ void gstore(T* p, T v) {
 #define CLF_PREFETCH64 2
 #endif
 #ifndef CLF_PREFETCH32
-#define CLF_PREFETCH32 1
+#define CLF_PREFETCH32 2
 #endif
 
 struct P64 {
   typedef double R;
-  // march rows between a row's load and its use (latency cover for the
-  // 3 waves per SIMD that the FP64 register footprint allows)
+  // march rows between a row's load and its use (latency cover)
   static constexpr int kPrefetch = CLF_PREFETCH64;
   // post-(a) view of a node along the sweep line: w normal, t tangential
   struct A { double H, w, t, D; int f; int pad; };
@@ -609,10 +616,10 @@ __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_i
   const int rc = r - 2;
   R iL = 1, iR = 1, iS = 1, tr = 0;
   if (rc >= 0 && rc < cx.ny) {
-    iL = gload(cx.yib + rc);
-    iR = gload(cx.yib + rc + 1);
-    iS = gload(cx.yisb + rc);
-    if (cx.par.flags & G_SPHSRC) tr = gload(cx.tanR + rc);
+    iL = cload(cx.yib + rc);
+    iR = cload(cx.yib + rc + 1);
+    iS = cload(cx.yisb + rc);
+    if (cx.par.flags & G_SPHSRC) tr = cload(cx.tanR + rc);
   }
   y.c[K] = P::stage_cd(P::bx(y.b[K1]), y.b[K2], P::bx(y.b[K]), iL, iR, iS, tr, cx.par);
   // (e) on row r-3
@@ -742,7 +749,7 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
         MW m = mnxt;
         load_row(r + 1, nxt);
         load_mw(r + 1, mnxt);
-        R f = gload(xfac + r);
+        R f = cload(xfac + r);
         C o = xsweep_row<P>(a, f * xiL, f * xiR, f * xiS, cx.par);
         store(r, o, a.D, m);
       }
@@ -779,13 +786,13 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
             ax.H = oy.H; ax.w = oy.t; ax.t = oy.w;
             ax.f = ob.f & (F_EX | F_FIX);
             ax.D = ob.D;
-            R f = gload(xfac + ro);
+            R f = cload(xfac + ro);
             C o = xsweep_row<P>(ax, f * xiL, f * xiR, f * xiS, cx.par);
             store(ro, o, ax.D, m);
           }
         } else {
           if (ORDER == ORD_XY && r >= 0 && r < ny) {
-            R f = gload(xfac + r);
+            R f = cload(xfac + r);
             C o = xsweep_row<P>(a, f * xiL, f * xiR, f * xiS, cx.par);
             a.H = o.H; a.w = o.w; a.t = o.t;
             a.f &= (F_EX | F_FIX);
