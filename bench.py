@@ -50,8 +50,15 @@ WORDS_PER_CELL_STEP = 11
 KERNEL_SRC = os.path.join(ROOT, "paper_1410_0753_amd", "csrc", "clf_kernels.hip")
 # Calibrated HBM bytes per launch of the step kernel, from rocprofv3 --pmc
 # FETCH_SIZE / WRITE_SIZE runs (profiles/), keyed by the sha256 of the kernel
-# source they were taken on.
-TRAFFIC = {}
+# source they were taken on and by workload; they apply only to a launch of
+# the same workgroup count (segment length).
+TRAFFIC = {
+    "64876febff4503d5c2d9efb84678739adfaadcd86f4684a8f438523ac057775e": {
+        "c2/fp64": {"workgroups": 760, "read_bytes": 271400000, "write_bytes": 110400000},
+        "c2/fp32": {"workgroups": 1192, "read_bytes": 154100000, "write_bytes": 52600000},
+        "c5/fp32": {"workgroups": 5072, "read_bytes": 1393800000, "write_bytes": 607300000},
+    },
+}
 
 
 def log(*a):
@@ -124,9 +131,11 @@ def run_grid(case, prec, steps, warmup, gauges=True, enclosed=False, bndout=1):
     r.sync()
     per_launch = ksecs / steps
     achieved = WORDS_PER_CELL_STEP * esize * case.cells / per_launch
+    blocks = int(r.query(clf.Q_BLOCKS))
     del r
     return {"value": case.cells * steps / secs, "ms_per_step": secs / steps * 1e3,
             "segment": seg, "kernel_ms": per_launch * 1e3, "achieved": achieved,
+            "workgroups": blocks,
             "ever_wet_frac_of_initially_dry": ever_wet,
             "enclosed_grids": len(case.enclosed) if kw else 0}
 
@@ -329,7 +338,14 @@ def main():
     head = run_grid(case, prec, args.steps, args.warmup)
     copy_bw = None if args.profile else copy_bandwidth()
     tkey = "%s/%s" % (args.workload, args.precision)
-    traffic = TRAFFIC.get(kernel_sha(), {}).get(tkey)
+    traffic = None
+    tr = TRAFFIC.get(kernel_sha(), {}).get(tkey)
+    if tr and tr["workgroups"] == head["workgroups"]:
+        tb = tr["read_bytes"] + tr["write_bytes"]
+        traffic = {"GBps": tb / (head["kernel_ms"] * 1e-3) / 1e9,
+                   "bytes_per_launch": tb, "read_bytes": tr["read_bytes"],
+                   "write_bytes": tr["write_bytes"],
+                   "algorithmic_bytes_per_launch": WORDS_PER_CELL_STEP * esize * case.cells}
     out = {
         "metric": METRIC,
         "value": head["value"],
