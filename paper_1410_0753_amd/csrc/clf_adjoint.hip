@@ -198,6 +198,178 @@ __device__ Nd flood_node(const Nd& L, const Nd& C, const Nd& R, const AdjPar& p)
   return b;
 }
 
+// ---------------------------------------------------------------------------
+// Reverse mode of the (c)+(d) update of one wet node k whose line neighbours
+// are wet or outside the grid (a missing neighbour is the mirror ghost of k).
+// Given the adjoint (gH, gW, gT) of node k's output (h, w, t), returns the
+// adjoints of the inputs (h, w, t) of nodes k-1, k, k+1: one evaluation per
+// output node, against three dual-number evaluations in the gather form.
+// The forward part repeats the kernel's operation order, so the clip of
+// stateh takes the forward decision.
+// ---------------------------------------------------------------------------
+struct NodeIn {
+  double H, w, t, D;
+};
+struct Vjp3 {
+  double LH, Lw, Lt, CH, Cw, Ct, RH, Rw, Rt;
+};
+
+__device__ __forceinline__ void qhat_rev(double la, double xa, double lb, double xb, double inv,
+                                         double g, double& gla, double& gxa, double& glb,
+                                         double& gxb) {
+  // Q = (0.5 (lb + la) (xb - xa) - g (Db - Da)) inv
+  const double gs = g * inv;
+  const double a = 0.5 * (xb - xa) * gs;
+  const double b = 0.5 * (lb + la) * gs;
+  gla += a; glb += a;
+  gxb += b; gxa -= b;
+}
+
+__device__ __forceinline__ Vjp3 vjp_local(const NodeIn& nl, const NodeIn& nc, const NodeIn& nr,
+                                          bool lex, bool rex, double iL, double iR, double iS,
+                                          double tanR, const AdjPar& p, double gH, double gW,
+                                          double gT) {
+  // ---- forward (same order as the step kernel) ----
+  const double Cw = nc.w, Ct = nc.t, CD = nc.D;
+  const double Cc = sqrt(kG * nc.H);
+  const double Lw = lex ? nl.w : -Cw, Lt = lex ? nl.t : Ct, LD = lex ? nl.D : CD;
+  const double Lc = lex ? sqrt(kG * nl.H) : Cc;
+  const double Rw = rex ? nr.w : -Cw, Rt = rex ? nr.t : Ct, RD = rex ? nr.D : CD;
+  const double Rc = rex ? sqrt(kG * nr.H) : Cc;
+  const double xPL = Lw + 2.0 * Lc, xPC = Cw + 2.0 * Cc, xPR = Rw + 2.0 * Rc;
+  const double lPL = Lw + Lc, lPC = Cw + Cc, lPR = Rw + Rc;
+  const double xML = Lw - 2.0 * Lc, xMC = Cw - 2.0 * Cc, xMR = Rw - 2.0 * Rc;
+  const double lML = Lw - Lc, lMC = Cw - Cc, lMR = Rw - Rc;
+  auto qh = [](double la, double xa, double Da, double lb, double xb, double Db, double inv) {
+    double s = lb + la;
+    double h = 0.5 * s;
+    double dx = xb - xa;
+    double m = h * dx;
+    double gd = kG * (Db - Da);
+    return (m - gd) * inv;
+  };
+  auto qt = [](double la, double xa, double lb, double xb, double inv) {
+    double s = lb + la;
+    double h = 0.5 * s;
+    double dx = xb - xa;
+    return (h * dx) * inv;
+  };
+  const bool s1 = (p.flags & G_SOLVER1) != 0;
+  const double QPL = qh(lPL, xPL, LD, lPC, xPC, CD, iL), QPR = qh(lPC, xPC, CD, lPR, xPR, RD, iR);
+  const double QML = qh(lML, xML, LD, lMC, xMC, CD, iL), QMR = qh(lMC, xMC, CD, lMR, xMR, RD, iR);
+  const double QTL = qt(Lw, Lt, Cw, Ct, iL), QTR = qt(Cw, Ct, Rw, Rt, iR);
+  auto adv = [&](double xi, double lam, double QL, double QR, double Qc) {
+    double a3 = s1 ? xi - p.dt * Qc : xi - p.hdt * (QL + QR);
+    double b3 = (lam * p.dt2) * (QR - QL);
+    return a3 + b3 * iS;
+  };
+  double QPc = 0.0, QMc = 0.0, QTc = 0.0;
+  if (s1) {
+    QPc = qh(lPL, xPL, LD, lPR, xPR, RD, iS);
+    QMc = qh(lML, xML, LD, lMR, xMR, RD, iS);
+    QTc = qt(Lw, Lt, Rw, Rt, iS);
+  }
+  double Pn = adv(xPC, lPC, QPL, QPR, QPc);
+  double Mn = adv(xMC, lMC, QML, QMR, QMc);
+  if (tanR != 0.0) {
+    const double s3 = ((p.dt * Cc) * Cw) * tanR;
+    Pn = Pn + s3;
+    Mn = Mn - s3;
+  }
+  const double dd = Pn - Mn;
+  const bool clipped = dd < 0.0;
+
+  // ---- reverse ----
+  double gCw = 0.0, gCt = 0.0, gCc = 0.0, gCH = 0.0;
+  double gLw = 0.0, gLt = 0.0, gLc = 0.0;
+  double gRw = 0.0, gRt = 0.0, gRc = 0.0;
+  double gwv = gW;
+  if (p.flags & G_FRICTION) {
+    const double wv0 = 0.5 * (Pn + Mn);
+    const double sp = sqrt(Cw * Cw + Ct * Ct);
+    const double cb = cbrt(nc.H);
+    const double den = nc.H * cb;
+    const double fr = ((p.dt * p.gn2) * sp) / den;
+    const double q = 1.0 + fr;
+    gwv = gW / q;
+    const double gfr = -gW * (wv0 / q) / q;
+    const double gsp = gfr * (p.dt * p.gn2) / den;
+    const double gden = -gfr * fr / den;
+    if (sp > 0.0) {
+      gCw += gsp * Cw / sp;
+      gCt += gsp * Ct / sp;
+    }
+    gCH += gden * (cb + nc.H * (1.0 / (3.0 * cb * cb)));
+  }
+  const double gdd = clipped ? 0.0 : gH * (2.0 * dd * p.inv16g);
+  double gPn = 0.5 * gwv + gdd;
+  double gMn = 0.5 * gwv - gdd;
+  if (tanR != 0.0) {
+    const double gs3 = gPn - gMn;
+    gCc += gs3 * (p.dt * Cw * tanR);
+    gCw += gs3 * (p.dt * Cc * tanR);
+  }
+  // advance: out = xi - hdt (QL + QR) [or - dt Qc] + (lam dt2 (QR - QL)) iS
+  double gxPL = 0, gxPC = 0, gxPR = 0, glPL = 0, glPC = 0, glPR = 0;
+  double gxML = 0, gxMC = 0, gxMR = 0, glML = 0, glMC = 0, glMR = 0;
+  auto adv_rev = [&](double g, double lam, double QL, double QR, double& gxi, double& glam,
+                     double& gQL, double& gQR, double& gQc) {
+    gxi += g;
+    if (s1) gQc = -p.dt * g;
+    else { gQL = -p.hdt * g; gQR = -p.hdt * g; }
+    const double k = g * p.dt2 * iS;
+    gQR += k * lam;
+    gQL -= k * lam;
+    glam += k * (QR - QL);
+  };
+  double gQPL = 0, gQPR = 0, gQPc = 0, gQML = 0, gQMR = 0, gQMc = 0, gQTL = 0, gQTR = 0, gQTc = 0;
+  adv_rev(gPn, lPC, QPL, QPR, gxPC, glPC, gQPL, gQPR, gQPc);
+  adv_rev(gMn, lMC, QML, QMR, gxMC, glMC, gQML, gQMR, gQMc);
+  adv_rev(gT, Cw, QTL, QTR, gCt, gCw, gQTL, gQTR, gQTc);
+  qhat_rev(lPL, xPL, lPC, xPC, iL, gQPL, glPL, gxPL, glPC, gxPC);
+  qhat_rev(lPC, xPC, lPR, xPR, iR, gQPR, glPC, gxPC, glPR, gxPR);
+  qhat_rev(lML, xML, lMC, xMC, iL, gQML, glML, gxML, glMC, gxMC);
+  qhat_rev(lMC, xMC, lMR, xMR, iR, gQMR, glMC, gxMC, glMR, gxMR);
+  qhat_rev(Lw, Lt, Cw, Ct, iL, gQTL, gLw, gLt, gCw, gCt);
+  qhat_rev(Cw, Ct, Rw, Rt, iR, gQTR, gCw, gCt, gRw, gRt);
+  if (s1) {
+    qhat_rev(lPL, xPL, lPR, xPR, iS, gQPc, glPL, gxPL, glPR, gxPR);
+    qhat_rev(lML, xML, lMR, xMR, iS, gQMc, glML, gxML, glMR, gxMR);
+    qhat_rev(Lw, Lt, Rw, Rt, iS, gQTc, gLw, gLt, gRw, gRt);
+  }
+  // xP = w + 2c, lP = w + c, xM = w - 2c, lM = w - c
+  gLw += gxPL + glPL + gxML + glML;
+  gLc += 2.0 * gxPL + glPL - 2.0 * gxML - glML;
+  gCw += gxPC + glPC + gxMC + glMC;
+  gCc += 2.0 * gxPC + glPC - 2.0 * gxMC - glMC;
+  gRw += gxPR + glPR + gxMR + glMR;
+  gRc += 2.0 * gxPR + glPR - 2.0 * gxMR - glMR;
+  Vjp3 o{};
+  // ghosts fold into the node itself: (h, -w, t) of k
+  if (lex) {
+    o.LH = gLc * (0.5 * kG / Lc);
+    o.Lw = gLw;
+    o.Lt = gLt;
+  } else {
+    gCw -= gLw;
+    gCt += gLt;
+    gCc += gLc;
+  }
+  if (rex) {
+    o.RH = gRc * (0.5 * kG / Rc);
+    o.Rw = gRw;
+    o.Rt = gRt;
+  } else {
+    gCw -= gRw;
+    gCt += gRt;
+    gCc += gRc;
+  }
+  o.CH = gCH + gCc * (0.5 * kG / Cc);
+  o.Cw = gCw;
+  o.Ct = gCt;
+  return o;
+}
+
 // Line accessor for one sweep: node index along the line -> memory index,
 // existence, inverse spacings and source factor.
 struct Line {
@@ -335,27 +507,8 @@ __device__ void adjoint_node(const Line& ln, int j, const AdjPar& p, const doubl
 __device__ __forceinline__ bool window_local(const Line& ln, int j, double hmin) {
   bool ok = true;
 #pragma unroll
-  for (int k = j - 4; k <= j + 4; ++k) ok &= wet_or_missing(ln, k, hmin);
+  for (int d = -4; d <= 4; ++d) ok &= wet_or_missing(ln, j + d, hmin);
   return ok;
-}
-
-// Adjoint of one sweep for input node j whose window is local (see above).
-__device__ __forceinline__ void adjoint_node_local(const Line& ln, int j, const AdjPar& p,
-                                                   const double* lH, const double* lW,
-                                                   const double* lT, double& aH, double& aW,
-                                                   double& aT) {
-  aH = 0.0; aW = 0.0; aT = 0.0;
-#pragma unroll
-  for (int k = j - 1; k <= j + 1; ++k) {
-    if (k < 0 || k >= ln.n) continue;
-    D3 Ho, wo, to;
-    block_local(ln, k, j, p, Ho, wo, to);
-    const long long m = ln.base + (long long)k * ln.step;
-    const double gH = lH[m], gW = lW[m], gT = lT[m];
-    aH += Ho.d0 * gH + wo.d0 * gW + to.d0 * gT;
-    aW += Ho.d1 * gH + wo.d1 * gW + to.d1 * gT;
-    aT += Ho.d2 * gH + wo.d2 * gW + to.d2 * gT;
-  }
 }
 
 // axis 0: lines are rows (w = u, t = v); axis 1: columns (w = v, t = u).
@@ -405,7 +558,7 @@ __device__ __forceinline__ Line make_line(const GridDesc& g, const SweepArgs& a,
   return ln;
 }
 
-template <int AXIS, bool GENERAL>
+template <int AXIS>
 __device__ __forceinline__ void sweep_node(const GridDesc& g, const SweepArgs& a, const Line& ln,
                                            const AdjPar& p, int i, int jrow) {
   const long long me = (long long)jrow * g.nx + i;
@@ -414,31 +567,136 @@ __device__ __forceinline__ void sweep_node(const GridDesc& g, const SweepArgs& a
   const double* lW = AXIS == 0 ? a.lamU : a.lamV;
   const double* lT = AXIS == 0 ? a.lamV : a.lamU;
   double aH, aW, aT;
-  if (GENERAL) adjoint_node(ln, j, p, a.lamH, lW, lT, aH, aW, aT);
-  else adjoint_node_local(ln, j, p, a.lamH, lW, lT, aH, aW, aT);
+  adjoint_node(ln, j, p, a.lamH, lW, lT, aH, aW, aT);
   a.outH[me] = aH;
   if (AXIS == 0) { a.outU[me] = aW; a.outV[me] = aT; }
   else { a.outV[me] = aW; a.outU[me] = aT; }
 }
 
-// Interior launch: one thread per node, grid (ceil(nx / kAdjBlock), ny).
-// Nodes whose window is local are done here (small register footprint);
-// a wavefront holding any other node sets its flag for the shoreline launch.
-template <int AXIS>
-__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(3))) void adjoint_local_kernel(GridDesc g, SweepArgs a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int jrow = blockIdx.y;
-  const bool in = i < g.nx;
+// Flag of the shoreline launch for node (i, row): one per 64 columns of a row
+// (the wavefronts of a 128-wide workgroup over the row).
+__device__ __forceinline__ int flag_index(int i, int row, int nx) {
+  const int gx = (nx + kAdjBlock - 1) / kAdjBlock;
+  return row * gx * (kAdjBlock / 64) + i / 64;
+}
+
+constexpr int kAdjStrip = 62;  // output nodes per wavefront of the x reverse sweep
+
+// Reverse of the x-sweep for the wet interior.  A wavefront covers nodes
+// k = 62 b - 1 + lane of one row; each lane forms the reverse-mode product of
+// its own node's update, and the three contributions to input node j come
+// from lanes j-1, j, j+1 by lane shuffles.  Lanes 1..62 write input nodes
+// whose window j-4..j+4 is wet or outside the grid; the others set the
+// shoreline flag.
+__global__ __launch_bounds__(64) void adjoint_local_x_kernel(GridDesc g, SweepArgs a) {
+  const int lane = threadIdx.x;
+  const int row = blockIdx.y;
+  const int nx = g.nx;
+  const int k = blockIdx.x * kAdjStrip - 1 + lane;
   const AdjPar p = adj_par(g);
-  const Line ln = make_line<AXIS>(g, a, in ? i : 0, jrow);
-  const bool local = in && window_local(ln, AXIS == 0 ? i : jrow, p.hmin);
-  const unsigned long long other = __ballot(in && !local);
-  if (other != 0 && (threadIdx.x & 63) == 0) {
-    const int wave = (blockIdx.y * gridDim.x + blockIdx.x) * (kAdjBlock / 64) + threadIdx.x / 64;
-    a.flags[wave] = 1;
+  const long long base = (long long)row * nx;
+  const double* H = a.preH;
+  const double* D = (const double*)g.D;
+  auto at = [&](int q) { return base + (q < 0 ? 0 : (q >= nx ? nx - 1 : q)); };
+  auto load = [&](int q) {
+    const long long m = at(q);
+    return NodeIn{H[m], a.preU[m], a.preV[m], D[m]};
+  };
+  const bool kex = k >= 0 && k < nx, lex = k - 1 >= 0, rex = k + 1 < nx;
+  const NodeIn nc = load(k), nl = load(k - 1), nr = load(k + 1);
+  const bool ok = kex && nc.H > p.hmin && (!lex || nl.H > p.hmin) && (!rex || nr.H > p.hmin);
+  Vjp3 v{};
+  if (ok) {
+    const double fac = ((const double*)g.xfac)[row];
+    const double* ib = (const double*)g.xib;
+    const long long m = base + k;
+    v = vjp_local(nl, nc, nr, lex, rex, fac * ib[k], fac * ib[k + 1],
+                  fac * ((const double*)g.xisb)[k], 0.0, p, a.lamH[m], a.lamU[m], a.lamV[m]);
   }
-  if (!local) return;
-  sweep_node<AXIS, false>(g, a, ln, p, i, jrow);
+  // contributions of the left neighbour's update (its R part) and of the
+  // right neighbour's (its L part)
+  const double fLH = __shfl_up(v.RH, 1), fLw = __shfl_up(v.Rw, 1), fLt = __shfl_up(v.Rt, 1);
+  const double fRH = __shfl_down(v.LH, 1), fRw = __shfl_down(v.Lw, 1),
+               fRt = __shfl_down(v.Lt, 1);
+  if (lane < 1 || lane > kAdjStrip || !kex) return;
+  bool local = true;
+#pragma unroll
+  for (int d = -4; d <= 4; ++d) {
+    const int q = k + d;
+    local &= (q < 0 || q >= nx || H[at(q)] > p.hmin);
+  }
+  if (!local) {
+    a.flags[flag_index(k, row, nx)] = 1;
+    return;
+  }
+  const long long m = base + k;
+  a.outH[m] = (fLH + v.CH) + fRH;
+  a.outU[m] = (fLw + v.Cw) + fRw;
+  a.outV[m] = (fLt + v.Ct) + fRt;
+}
+
+// Reverse of the y-sweep for the wet interior.  A wavefront covers 64
+// columns and marches down a band of rows; at row r each lane forms the
+// reverse-mode product of node r's update and writes input node r-1 from
+// the products of rows r-2, r-1 and r held in registers.
+__global__ __launch_bounds__(64) void adjoint_local_y_kernel(GridDesc g, SweepArgs a, int seg) {
+  const int lane = threadIdx.x;
+  const int nx = g.nx, ny = g.ny;
+  const int i = blockIdx.x * 64 + lane;
+  const bool col = i < nx;
+  const int ic = col ? i : nx - 1;
+  const int y0 = blockIdx.y * seg;
+  const int y1 = y0 + seg < ny ? y0 + seg : ny;
+  const AdjPar p = adj_par(g);
+  const double* H = a.preH;
+  const double* D = (const double*)g.D;
+  const double* yib = (const double*)g.yib;
+  const double* yisb = (const double*)g.yisb;
+  const double* tanR = (g.flags & G_SPHSRC) ? (const double*)g.tanR : nullptr;
+  auto at = [&](int r) { return (long long)(r < 0 ? 0 : (r >= ny ? ny - 1 : r)) * nx + ic; };
+  // y view: w = v, t = u
+  auto load = [&](int r) {
+    const long long m = at(r);
+    return NodeIn{H[m], a.preV[m], a.preU[m], D[m]};
+  };
+  auto wom = [&](int r) { return (r < 0 || r >= ny || H[at(r)] > p.hmin) ? 1u : 0u; };
+  // bit b of wb: row r+3-b is wet or outside the grid (b = 0..8 at row r)
+  unsigned wb = 0;
+  for (int rr = y0 - 6; rr <= y0 + 1; ++rr) wb = (wb << 1) | wom(rr);
+  NodeIn nl = load(y0 - 2), nc = load(y0 - 1);
+  double R2H = 0, R2w = 0, R2t = 0;  // row r-2's contribution to row r-1
+  double R1H = 0, R1w = 0, R1t = 0;  // row r-1's contribution to row r
+  double C1H = 0, C1w = 0, C1t = 0;  // row r-1's contribution to itself
+  for (int r = y0 - 1; r <= y1; ++r) {
+    const NodeIn nr = load(r + 1);
+    wb = (wb << 1) | wom(r + 3);
+    const bool rin = r >= 0 && r < ny;
+    const bool lex = r - 1 >= 0, rex = r + 1 < ny;
+    const bool ok = col && rin && nc.H > p.hmin && (!lex || nl.H > p.hmin) &&
+                    (!rex || nr.H > p.hmin);
+    Vjp3 v{};
+    if (ok) {
+      const long long m = (long long)r * nx + i;
+      v = vjp_local(nl, nc, nr, lex, rex, yib[r], yib[r + 1], yisb[r], tanR ? tanR[r] : 0.0, p,
+                    a.lamH[m], a.lamV[m], a.lamU[m]);
+    }
+    const int j = r - 1;
+    if (j >= y0) {
+      const bool local = (wb & 0x1FFu) == 0x1FFu;
+      if (__ballot(col && !local) != 0 && lane == 0) a.flags[flag_index(blockIdx.x * 64, j, nx)] = 1;
+      if (col && local) {
+        const long long m = (long long)j * nx + i;
+        a.outH[m] = (R2H + C1H) + v.LH;
+        a.outV[m] = (R2w + C1w) + v.Lw;
+        a.outU[m] = (R2t + C1t) + v.Lt;
+      }
+    }
+    R2H = R1H; R2w = R1w; R2t = R1t;
+    R1H = v.RH; R1w = v.Rw; R1t = v.Rt;
+    C1H = v.CH; C1w = v.Cw; C1t = v.Ct;
+    nl = nc;
+    nc = nr;
+  }
 }
 
 // Shoreline launch: one wavefront per workgroup, grid-stride over the
@@ -456,7 +714,7 @@ __global__ __launch_bounds__(64) void adjoint_general_kernel(GridDesc g, SweepAr
     const int i = (b % gx) * kAdjBlock + part * 64 + (int)threadIdx.x;
     if (i < g.nx) {
       const Line ln = make_line<AXIS>(g, a, i, jrow);
-      if (!window_local(ln, AXIS == 0 ? i : jrow, p.hmin)) sweep_node<AXIS, true>(g, a, ln, p, i, jrow);
+      if (!window_local(ln, AXIS == 0 ? i : jrow, p.hmin)) sweep_node<AXIS>(g, a, ln, p, i, jrow);
     }
     __syncthreads();
     if (threadIdx.x == 0) a.flags[w] = 0;
@@ -512,12 +770,17 @@ hipError_t launch_adjoint_sweep(const GridDesc* gd_host, int axis, const double*
   const int gx = (gd_host->nx + kAdjBlock - 1) / kAdjBlock;
   const int nwaves = adjoint_flag_count(gd_host->nx, gd_host->ny);
   const int nb = nwaves < 1024 ? nwaves : 1024;
-  const dim3 grid(gx, gd_host->ny), block(kAdjBlock);
   if (axis == 0) {
-    hipLaunchKernelGGL(adjoint_local_kernel<0>, grid, block, 0, s, *gd_host, a);
+    const dim3 gxs((gd_host->nx + kAdjStrip - 1) / kAdjStrip, gd_host->ny);
+    hipLaunchKernelGGL(adjoint_local_x_kernel, gxs, dim3(64), 0, s, *gd_host, a);
     hipLaunchKernelGGL(adjoint_general_kernel<0>, dim3(nb), dim3(64), 0, s, *gd_host, a, nwaves, gx);
   } else {
-    hipLaunchKernelGGL(adjoint_local_kernel<1>, grid, block, 0, s, *gd_host, a);
+    // row bands: enough wavefronts to fill the GPU, at least 8 rows each
+    const int nbx = (gd_host->nx + 63) / 64;
+    long long sg = (long long)nbx * gd_host->ny / 4096;
+    const int seg = (int)(sg < 8 ? 8 : (sg > 64 ? 64 : sg));
+    const dim3 gys(nbx, (gd_host->ny + seg - 1) / seg);
+    hipLaunchKernelGGL(adjoint_local_y_kernel, gys, dim3(64), 0, s, *gd_host, a, seg);
     hipLaunchKernelGGL(adjoint_general_kernel<1>, dim3(nb), dim3(64), 0, s, *gd_host, a, nwaves, gx);
   }
   return hipGetLastError();

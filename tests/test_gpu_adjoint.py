@@ -57,6 +57,32 @@ def test_adjoint_dot_product_vs_complex_step(clf, oracle_mod, land):
         assert abs(ad - dL) <= 1e-9 * max(abs(dL), 1e-30) + 1e-14
 
 
+@pytest.mark.parametrize("variant", ["spherical", "solver1", "friction"])
+def test_adjoint_variants_vs_complex_step(clf, oracle_mod, variant):
+    # the reverse-mode interior path and the shoreline path under the
+    # spherical continuity source (y-sweep), the solver1 stencil and friction
+    kw = {"solver1": dict(solver=1), "friction": dict(manning_n2=0.0009)}.get(variant, {})
+    coord = synth.SPHERICAL if variant == "spherical" else synth.CARTESIAN
+    c = synth.random_small(60, 66, 48, land=True, amp=0.3, coord=coord)
+    nsteps = 30
+    gx = np.array([6, 33, 58, 40]); gy = np.array([9, 24, 38, 5])
+    s = clf.Solver.from_case(c, gout=3, **kw)
+    s.set_gauges(gx, gy)
+    o = oracle_mod.Oracle.from_case(c, gout=3, **kw)
+    o.set_gauges(gx, gy)
+    nrec = nsteps // 3 + 1
+    obs = 0.05 * np.random.default_rng(4).standard_normal((nrec, len(gx)))
+    L, g = misfit_grad(s, c.eta0, nsteps, obs)
+    rng = np.random.default_rng(11)
+    for trial in range(2):
+        d = rng.standard_normal(c.eta0.shape) * (c.depth > 0)
+        Lo, dL = o.cs_gauge_loss(c.eta0, d, nsteps, obs)
+        assert abs(Lo - L) <= 1e-12 * abs(L)
+        ad = float(np.sum(g * d))
+        print(variant, trial, ad, dL)
+        assert abs(ad - dL) <= 1e-9 * max(abs(dL), 1e-30) + 1e-14
+
+
 def test_adjoint_vs_finite_differences(clf):
     case, basis, c_true, c0 = synth.config4(nx=120, ny=96, steps=200, nsrc=6, ngauge=8)
     nsteps = 200
