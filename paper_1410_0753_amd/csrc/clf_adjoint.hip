@@ -6,14 +6,18 @@
 // stateh frozen at the forward values, node k's output depends on the inputs
 // at k-3..k+3 (radius 1 where the neighbourhood is wet and nothing floods).
 // The adjoint of a sweep is the transposed Jacobian-vector product
-//     lambda_in[j] = sum_{k=j-3..j+3} (d out_k / d in_j)^T lambda_out[k],
-// gathered per input node j (deterministic, no atomics).  Each 3x3 block
-// d out_k / d in_j (fields h, w, t) is obtained by evaluating node k's
-// update once in a forward-mode dual number carrying the three directions
-// of in_j.  The node update below restates the step of the paper (eqQ,
-// solver2/solver1, stateu/stateh, inundation (a)-(e)) for one node from a
-// window of the pre-sweep state, in the same operation order as the
-// forward kernel, so its real part reproduces the forward decisions.
+//     lambda_in[j] = sum_{k=j-3..j+3} (d out_k / d in_j)^T lambda_out[k]
+// (deterministic, no atomics).  In the wet interior only k = j-1..j+1
+// contribute, each through the radius-1 update (c)+(d): every output node
+// forms its own product once in hand-written reverse mode and the three
+// contributions are gathered (lane shuffles along x, a register march down
+// the columns along y).  Near the shoreline each 3x3 block d out_k / d in_j
+// (fields h, w, t) comes from evaluating node k's update (a)-(e) once in a
+// forward-mode dual number carrying the three directions of in_j.  Both
+// restate the step of the paper (eqQ, solver2/solver1, stateu/stateh,
+// inundation (a)-(e)) for one node from a window of the pre-sweep state, in
+// the forward kernel's operation order, so that the branch decisions are
+// the forward ones.
 
 #include "clf_internal.h"
 
