@@ -703,25 +703,32 @@ __global__ __launch_bounds__(64) void adjoint_local_y_kernel(GridDesc g, SweepAr
   }
 }
 
-// Shoreline launch: one wavefront per workgroup, grid-stride over the
-// interior launch's wavefronts; a flagged one is redone here for its
-// non-local nodes, and its flag is cleared for the next sweep.
+// Shoreline launch: one wavefront per workgroup, grid-stride over chunks of
+// 64 flags of the interior launches: the lanes read a chunk at once, and
+// each flagged wavefront of it is redone here for its non-local nodes, and
+// its flag cleared for the next sweep.
 template <int AXIS>
 __global__ __launch_bounds__(64) void adjoint_general_kernel(GridDesc g, SweepArgs a, int nwaves,
                                                              int gx) {
   constexpr int kWpb = kAdjBlock / 64;
   const AdjPar p = adj_par(g);
-  for (int w = blockIdx.x; w < nwaves; w += gridDim.x) {
-    if (a.flags[w] == 0) continue;
-    const int b = w / kWpb, part = w % kWpb;
-    const int jrow = b / gx;
-    const int i = (b % gx) * kAdjBlock + part * 64 + (int)threadIdx.x;
-    if (i < g.nx) {
-      const Line ln = make_line<AXIS>(g, a, i, jrow);
-      if (!window_local(ln, AXIS == 0 ? i : jrow, p.hmin)) sweep_node<AXIS>(g, a, ln, p, i, jrow);
+  const int lane = threadIdx.x;
+  const int nchunks = (nwaves + 63) / 64;
+  for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const int wl = c * 64 + lane;
+    unsigned long long set = __ballot(wl < nwaves && a.flags[wl] != 0);
+    while (set != 0) {
+      const int w = c * 64 + (__ffsll((unsigned long long)set) - 1);
+      set &= set - 1;
+      const int b = w / kWpb, part = w % kWpb;
+      const int jrow = b / gx;
+      const int i = (b % gx) * kAdjBlock + part * 64 + lane;
+      if (i < g.nx) {
+        const Line ln = make_line<AXIS>(g, a, i, jrow);
+        if (!window_local(ln, AXIS == 0 ? i : jrow, p.hmin)) sweep_node<AXIS>(g, a, ln, p, i, jrow);
+      }
+      if (lane == 0) a.flags[w] = 0;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) a.flags[w] = 0;
   }
 }
 
@@ -773,7 +780,8 @@ hipError_t launch_adjoint_sweep(const GridDesc* gd_host, int axis, const double*
   SweepArgs a{preH, preU, preV, lamH, lamU, lamV, outH, outU, outV, flags};
   const int gx = (gd_host->nx + kAdjBlock - 1) / kAdjBlock;
   const int nwaves = adjoint_flag_count(gd_host->nx, gd_host->ny);
-  const int nb = nwaves < 1024 ? nwaves : 1024;
+  const int nchunks = (nwaves + 63) / 64;
+  const int nb = nchunks < 1024 ? nchunks : 1024;
   if (axis == 0) {
     const dim3 gxs((gd_host->nx + kAdjStrip - 1) / kAdjStrip, gd_host->ny);
     hipLaunchKernelGGL(adjoint_local_x_kernel, gxs, dim3(64), 0, s, *gd_host, a);
