@@ -1,7 +1,7 @@
 """Benchmark of the split step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload c2|c5|c1|ensemble|adjoint]
+                    [--workload c2|c5|c1|ensemble|adjoint|c5err]
                     [--precision fp64|fp32] [--no-cpu] [--no-extras] [--profile]
 
 Headline (default): the 2400 x 1800 spherical grid at 1 arc-minute (seeded
@@ -30,7 +30,13 @@ extras (same line): the FP32 run of the headline grid with its error
 against the FP64 oracle; the 8000 x 6000 spherical grid (FP32 and FP64, with
 its 4 enclosed-grid boundary series every step); the 64-member
 ensemble against sequential single-grid solves; the adjoint gradient of the
-1000 x 800 inversion problem against a finite-difference gradient.
+1000 x 800 inversion problem against a finite-difference gradient (and an
+estimate of the same gradient by the host oracle); the oracle's rate on the
+200 x 200 and 8000 x 6000 grids.
+
+--workload c5err (not part of the default run) reports the FP32 error on the
+8000 x 6000 grid: against the FP64 oracle after min(K, 50) steps and against
+the FP64 GPU path after K steps.
 """
 from __future__ import annotations
 
@@ -211,7 +217,7 @@ def run_ensemble(steps, n=64):
             "roofline_frac": cells * steps / tb * WORDS_PER_CELL_STEP * 4 / PEAK_HBM}
 
 
-def run_adjoint(steps=3000):
+def run_adjoint(steps=3000, cpu_fd=False):
     import numpy as np
     import torch
     from paper_1410_0753_amd import clf, synth
@@ -253,7 +259,23 @@ def run_adjoint(steps=3000):
         fd[k] = (loss(c0 + e) - loss(c0 - e)) / (2 * h)
     t_fd = time.perf_counter() - t0
     rel = float(np.max(np.abs(g - fd)) / np.max(np.abs(fd)))
-    return {"grid": "%dx%d" % (case.nx, case.ny), "steps": steps, "sources": len(c0),
+    extra = {}
+    if cpu_fd:
+        # the same finite-difference gradient on the host oracle, estimated
+        # from a timed 50-step forward solve with the gauges recorded
+        import oracle
+        o = oracle.Oracle.from_case(case, gout=1)
+        o.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
+        o.set_initial(case.eta0)
+        t0 = time.perf_counter()
+        o.step(50)
+        per = (time.perf_counter() - t0) / 50
+        extra = {"cpu_oracle_fd_s_estimate": 2 * len(c0) * steps * per,
+                 "cpu_oracle_fd_basis": "50-step oracle sample on %d threads, scaled to %d solves "
+                                        "of %d steps" % (oracle.set_threads(0), 2 * len(c0), steps)}
+        extra["speedup_vs_cpu_oracle_fd"] = extra["cpu_oracle_fd_s_estimate"] / t_adj
+        del o
+    return {**extra, "grid": "%dx%d" % (case.nx, case.ny), "steps": steps, "sources": len(c0),
             "gauges": int(len(case.gauges)), "checkpoint_every": int(np.ceil(np.sqrt(steps))),
             "adjoint_s": t_adj, "fd_s": t_fd, "speedup_vs_fd": t_fd / t_adj,
             "max_rel_diff_vs_fd": rel}
@@ -284,6 +306,73 @@ def cpu_baseline(case, budget_s=12.0):
                       "%.1f s" % (k, case.nx, case.ny, t1 - t0),
             "single_thread_value": case.cells * k1 / (t3 - t2),
             "single_thread_sample": "%d further steps on 1 thread, %.1f s" % (k1, t3 - t2)}
+
+
+def cpu_other(cases):
+    """The oracle on other workloads: steps per second on a few full steps
+    (after one warm-up step), all host threads."""
+    import oracle
+    out = {}
+    for name, case, k in cases:
+        o = oracle.Oracle.from_case(case)
+        o.set_initial(case.eta0, case.u0, case.v0)
+        o.step(1)
+        t0 = time.perf_counter()
+        o.step(k)
+        dt = time.perf_counter() - t0
+        out[name] = {"cell_updates_per_s": case.cells * k / dt, "steps": k,
+                     "grid": "%dx%d" % (case.nx, case.ny), "seconds": dt}
+        del o
+    out["cores"] = oracle.set_threads(0)
+    return out
+
+
+def fp32_error_large(steps, oracle_steps):
+    """FP32 on the 8000x6000 grid against the FP64 oracle after
+    `oracle_steps` steps, and against the FP64 GPU path (bitwise equal to the
+    oracle on every parity test) after `steps` steps."""
+    import numpy as np
+    import oracle
+    from paper_1410_0753_amd import clf, synth
+    case = synth.config5(steps=steps)
+
+    def run(prec, n):
+        s = clf.Solver.from_case(case, precision=prec, maxout=1, autotune=1)
+        s.set_initial(case.eta0, case.u0, case.v0)
+        dry0 = (s.state()[3] == 0).cpu().numpy()
+        s.step(n)
+        e, _, _, w = (t.cpu().numpy() for t in s.state())
+        em = s.read_maxwave()[0].cpu().numpy()
+        del s
+        return e, w, em, dry0
+
+    def compare(ea, wa, eb, wb):
+        amp = float(np.abs(eb).max())
+        err = np.abs(ea - eb)
+        return {"max_eta_err_rel": float(err.max() / amp),
+                "rms_eta_err_rel": float(np.sqrt((err ** 2).mean()) / amp),
+                "mask_flip_frac": float((wa.astype(bool) != wb.astype(bool)).mean())}
+
+    log("fp32 vs oracle, %d steps ..." % oracle_steps)
+    e32, w32, _, _ = run(clf.FP32, oracle_steps)
+    o = oracle.Oracle.from_case(case)
+    o.set_initial(case.eta0, case.u0, case.v0)
+    t0 = time.perf_counter()
+    o.step(oracle_steps)
+    to = time.perf_counter() - t0
+    eo, _, _, wo = o.state()
+    del o
+    res = {"workload": case.name, "vs_fp64_oracle": dict(steps=oracle_steps, oracle_s=to,
+                                                         **compare(e32, w32, eo, wo))}
+    log("fp32 vs fp64 gpu, %d steps ..." % steps)
+    e32, w32, m32, dry0 = run(clf.FP32, steps)
+    e64, w64, m64, _ = run(clf.FP64, steps)
+    ew32, ew64 = (m32 > 0) & dry0, (m64 > 0) & dry0
+    res["vs_fp64_gpu"] = dict(steps=steps, **compare(e32, w32, e64, w64))
+    res["vs_fp64_gpu"]["ever_wet_of_initially_dry_fp32"] = float(ew32.sum() / max(1, dry0.sum()))
+    res["vs_fp64_gpu"]["ever_wet_of_initially_dry_fp64"] = float(ew64.sum() / max(1, dry0.sum()))
+    res["vs_fp64_gpu"]["ever_wet_flip_frac"] = float((ew32 != ew64).mean())
+    return res
 
 
 def main():
@@ -319,6 +408,11 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.workload == "c5err":
+        # long-run FP32 error report on the 8000x6000 grid (not in the default run)
+        res = fp32_error_large(args.steps, min(args.steps, 50))
+        print(json.dumps({"metric": METRIC, "workload": "c5err", "fp32_error": res}), flush=True)
+        return
     if args.workload in ("ensemble", "adjoint"):
         # one extras leg alone (for profilers)
         torch.cuda.set_device(0)
@@ -405,7 +499,11 @@ def main():
         log("ensemble ...")
         extras["ensemble"] = run_ensemble(min(args.steps, 300))
         log("adjoint ...")
-        extras["adjoint"] = run_adjoint(3000)
+        extras["adjoint"] = run_adjoint(3000, cpu_fd=not args.no_cpu)
+        if not args.no_cpu:
+            log("oracle on the other workloads ...")
+            extras["cpu_other"] = cpu_other([("200x200", synth.config1(steps=10), 400),
+                                             ("8000x6000", synth.config5(steps=10), 2)])
         out["extras"] = extras
     print(json.dumps(out), flush=True)
 

@@ -182,6 +182,7 @@ class Solver:
     @classmethod
     def from_case(cls, case, **kw):
         kw.setdefault("h_min", case.h_min)
+        kw.setdefault("manning_n2", getattr(case, "manning_n2", 0.0))
         return cls(case.x, case.y, case.depth, case.dt, coord=case.coord, **kw)
 
     # -- errors --

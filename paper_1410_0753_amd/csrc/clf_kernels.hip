@@ -270,9 +270,16 @@ struct P64 {
     dd = (dd < 0.0) ? 0.0 : dd;
     double Hv = (dd * dd) * p.inv16g;
     if (p.flags & G_FRICTION) {
+      // k sp / h^(4/3) with h^(-1/3) from a single-precision seed (hardware
+      // log2 / exp2) and two Newton steps r <- r (4 - h r^3) / 3: no libm
+      // cbrt and no division; agrees with the direct form to rounding
       double sp = sqrt(Cw * Cw + Ct * Ct);
-      double den = c.H * cbrt(c.H);
-      double fr = ((p.dt * p.gn2) * sp) / den;
+      const double h = c.H;
+      double r = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)h) * (-1.0f / 3.0f));
+      r = r * ((4.0 - h * ((r * r) * r)) * (1.0 / 3.0));
+      r = r * ((4.0 - h * ((r * r) * r)) * (1.0 / 3.0));
+      const double r2 = r * r;
+      double fr = ((p.dt * p.gn2) * sp) * (r2 * r2);
       wv = wv / (1.0 + fr);
     }
     const bool wet = (c.f & F_WET) != 0;
@@ -467,10 +474,11 @@ struct P32 {
     const float hv = drained ? 0.f : c.h + dh;
     const float ev = drained ? -CD : Ce + dh;
     if (p.flags & G_FRICTION) {
-      const float sp = sqrtf(Cw * Cw + Ct * Ct);
-      const float den = c.h * cbrtf(c.h);
-      const float fr = ((p.dt * p.gn2) * sp) / den;
-      wv = wv / (1.f + fr);
+      // k sp h^(-4/3) through the hardware log2 / exp2 and reciprocal
+      const float sp = __builtin_amdgcn_sqrtf(Cw * Cw + Ct * Ct);
+      const float hm43 = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(c.h) * (-4.0f / 3.0f));
+      const float fr = ((p.dt * p.gn2) * sp) * hm43;
+      wv = wv * __builtin_amdgcn_rcpf(1.f + fr);
     }
     const bool wet = (c.f & F_WET) != 0;
     C o;
@@ -630,6 +638,8 @@ __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_i
 
 // FL: the grid flags this instantiation honours (others are compiled out).
 constexpr int FL_FAST = G_SPHSRC;
+// runup workloads: the common case plus bottom friction
+constexpr int FL_FRIC = G_SPHSRC | G_FRICTION;
 constexpr int FL_ALL = G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N | G_WALLMODE | G_SOLVER1 |
                        G_SPHSRC | G_FRICTION;
 
@@ -1096,14 +1106,19 @@ hipError_t launch_step(int fp32, int order, int gflags, const GridDesc* grids, c
                        hipStream_t s) {
   dim3 grid(nblocks), block(WAVE * WAVES_PER_BLOCK);
   const bool fast = (gflags & ~FL_FAST) == 0;
+  const bool fric = (gflags & ~FL_FRIC) == 0;
   if (fp32) {
     if (fast)
       launch_order<P32, FL_FAST>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+    else if (fric)
+      launch_order<P32, FL_FRIC>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
     else
       launch_order<P32, FL_ALL>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
   } else {
     if (fast)
       launch_order<P64, FL_FAST>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+    else if (fric)
+      launch_order<P64, FL_FRIC>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
     else
       launch_order<P64, FL_ALL>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
   }
@@ -1132,8 +1147,12 @@ static hipError_t occupancy_of(int order, int* n) {
 hipError_t step_blocks_per_cu(int fp32, int order, int gflags, int* n) {
   *n = 0;
   const bool fast = (gflags & ~FL_FAST) == 0;
-  if (fp32) return fast ? occupancy_of<P32, FL_FAST>(order, n) : occupancy_of<P32, FL_ALL>(order, n);
-  return fast ? occupancy_of<P64, FL_FAST>(order, n) : occupancy_of<P64, FL_ALL>(order, n);
+  const bool fric = (gflags & ~FL_FRIC) == 0;
+  if (fp32)
+    return fast ? occupancy_of<P32, FL_FAST>(order, n)
+                : (fric ? occupancy_of<P32, FL_FRIC>(order, n) : occupancy_of<P32, FL_ALL>(order, n));
+  return fast ? occupancy_of<P64, FL_FAST>(order, n)
+              : (fric ? occupancy_of<P64, FL_FRIC>(order, n) : occupancy_of<P64, FL_ALL>(order, n));
 }
 
 #define CLF_SMALL_LAUNCH(KERNEL, N, ...)                                           \

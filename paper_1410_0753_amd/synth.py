@@ -45,6 +45,7 @@ class Case:
     gauges: Optional[np.ndarray] = None   # [ng, 2] int32 (ix, iy), 0-based
     enclosed: Optional[List[tuple]] = None  # list of (x, y) coordinate vectors
     extra: Optional[dict] = None
+    manning_n2: float = 0.0   # bottom friction (Manning n^2); 0 = off
 
     @property
     def nx(self) -> int:
@@ -154,12 +155,20 @@ def config1(nx=200, ny=200, steps=1000, seed_id=1) -> Case:
 # Config 2: spherical 2400x1800 at 1 arc-min, land band, shelf, slope, dipole.
 # --------------------------------------------------------------------------
 def _coastal_profile(i, land_cells, shelf_cells, shelf_d=150.0, deep_d=4000.0,
-                     slope_cells=100, land_top=20.0):
-    """Depth as a function of the cell distance i from the land edge."""
+                     slope_cells=100, land_top=20.0, beach_cells=10):
+    """Depth as a function of the cell distance i from the land edge.
+
+    The shelf meets the land through a linear beach of `beach_cells` cells
+    (shelf_d / beach_cells metres per cell): a shelf standing directly against
+    the land is a cliff of shelf_d metres, which runup over it cannot pass
+    stably in this scheme, and which the depth preprocessing leaves in place
+    (its ratio test looks at wet neighbours only)."""
     i = np.asarray(i, dtype=np.float64)
     land = -land_top * (land_cells - i) / land_cells
     centre = land_cells + shelf_cells + slope_cells / 2.0
     sea = shelf_d + (deep_d - shelf_d) * 0.5 * (1.0 + np.tanh((i - centre) / (slope_cells / 4.0)))
+    ramp = shelf_d * (i - land_cells + 1.0) / max(beach_cells, 1)
+    sea = np.where(i < land_cells + beach_cells, np.minimum(sea, ramp), sea)
     return np.where(i < land_cells, land, sea)
 
 
@@ -340,8 +349,12 @@ def config5(steps=20000, scale=1, seed_id=5, amp=3.0) -> Case:
         x0 = min(max(cxs - ne * de / 2, x[1]), x[-2] - ne * de)
         y0 = min(max(cys - ne * de / 2, y[1]), y[-2] - ne * de)
         enclosed.append((f32(x0 + np.arange(ne) * de), f32(y0 + np.arange(ne) * de)))
+    # runup over the land: Manning n^2 = 0.0009, the value of the paper's 2-D
+    # example parameter files (without friction, thin layers on the coastal
+    # plain reach hundreds of m/s and the run leaves the Courant limit)
     return Case("C5 spherical 0.5-arcmin %dx%d" % (nx, ny), SPHERICAL, f32(x), f32(y),
-                depth, eta0, zeros, zeros.copy(), dt, steps, 0.1, g, enclosed)
+                depth, eta0, zeros, zeros.copy(), dt, steps, 0.1, g, enclosed,
+                manning_n2=0.0009)
 
 
 # --------------------------------------------------------------------------

@@ -108,8 +108,9 @@ def test_option_parity(clf, oracle_mod, opts):
     _cmp_state(g, o, bitwise=True, what=str(opts))
 
 
-def test_friction_parity(clf, oracle_mod):
-    case = synth.random_small(8, 80, 60, land=True)
+@pytest.mark.parametrize("coord", [synth.CARTESIAN, synth.SPHERICAL], ids=["cartesian", "spherical"])
+def test_friction_parity(clf, oracle_mod, coord):
+    case = synth.random_small(8, 80, 60, land=True, coord=coord)
     g, o = _pair(clf, case, oracle_mod, manning_n2=0.0009)
     for obj in (g, o):
         obj.set_initial(case.eta0 * 2.0, case.u0, case.v0)
