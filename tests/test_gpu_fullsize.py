@@ -87,3 +87,25 @@ def test_zero_steps_and_errors(clf):
         g.step(-1)
     with pytest.raises(clf.ClfError):
         clf.Solver.from_case(case, segment=3)
+
+
+@pytest.mark.parametrize("wl", ["2400x1800", "8000x6000"])
+def test_full_length_runs_stay_finite(clf, wl):
+    # the configured run lengths of the two spherical workloads (10000 and
+    # 20000 steps) stay finite with bounded speeds: the beach between land
+    # and shelf, and friction on the runup grid
+    import torch
+    case = synth.config2(steps=10000) if wl == "2400x1800" else synth.config5(steps=20000)
+    precs = [clf.FP64, clf.FP32] if wl == "2400x1800" else [clf.FP32]
+    for prec in precs:
+        print("full length", wl, "fp32" if prec == clf.FP32 else "fp64", case.steps, flush=True)
+        g = clf.Solver.from_case(case, precision=prec, maxout=1, autotune=1)
+        g.set_initial(case.eta0, case.u0, case.v0)
+        g.step(case.steps)
+        g.sync()
+        e, u, v, _ = g.state()
+        smax = float(torch.sqrt(u * u + v * v).max())
+        emax = float(e.abs().max())
+        print("  max speed %.3f max |eta| %.3f" % (smax, emax), flush=True)
+        assert smax < 50.0 and emax < 50.0
+        del g
