@@ -65,3 +65,64 @@ def test_grid_size_limits(lib):
     ok = clf.Grid(65536, 65535, 0, px, px)
     assert lib.clf_workspace_bytes(ctypes.byref(ok), ctypes.byref(p), ctypes.byref(n)) == 0
     assert n.value >= 9 * 8 * 65536 * 65535
+
+
+def _ws(lib, grid, params):
+    import ctypes as C
+    n = C.c_size_t(0)
+    lib.clf_workspace_bytes.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    return lib.clf_workspace_bytes(C.byref(grid), C.byref(params), C.byref(n))
+
+
+@pytest.mark.parametrize("field,value", [
+    ("precision", 7), ("h_min", 0.0), ("h_min", -1.0), ("manning_n2", -0.1), ("solver", 3),
+    ("sweep_order", 5), ("maxout", 0), ("gout", 0), ("bndout", 0), ("ssl_alpha", 0.5),
+    ("max_gauges", -1), ("gauge_capacity", -1), ("series_capacity", -1),
+    ("earth_radius", 0.0), ("segment", 3), ("segment", 5000), ("graph_steps", 3),
+    ("graph_steps", -2), ("persistent_blocks", 12), ("persistent_blocks", -8),
+])
+def test_parameter_validation(lib, field, value):
+    # every parameter outside its documented range is rejected with CLF_EINVAL
+    # before anything touches a device
+    from paper_1410_0753_amd import clf
+    import numpy as np
+    x = np.arange(40.0); y = np.arange(30.0)
+    px = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    py = y.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p = clf.Params()
+    lib.clf_default_params(ctypes.byref(p))
+    g = clf.Grid(40, 30, 0, px, py)
+    assert _ws(lib, g, p) == 0
+    setattr(p, field, value)
+    assert _ws(lib, g, p) == -1
+
+
+def test_grid_validation(lib):
+    from paper_1410_0753_amd import clf
+    import numpy as np
+    p = clf.Params()
+    lib.clf_default_params(ctypes.byref(p))
+
+    def ws(nx, ny, x, y, coord=0):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        g = clf.Grid(nx, ny, coord, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                     y.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return _ws(lib, g, p)
+
+    assert ws(3, 3, [0, 1, 2], [0, 1, 2]) == 0
+    assert ws(1, 3, [0], [0, 1, 2]) == 0            # 1-D along y
+    assert ws(3, 1, [0, 1, 2], [0]) == 0            # 1-D along x
+    assert ws(1, 2, [0], [0, 1]) == -1              # 1-D needs 3 nodes
+    assert ws(2, 5, [0, 1], np.arange(5)) == -1     # 2-D needs 3 per axis
+    assert ws(0, 5, [0], np.arange(5)) == -1
+    assert ws(3, 3, [0, 2, 1], [0, 1, 2]) == -1     # x not increasing
+    assert ws(3, 3, [0, 1, 2], [0, 1, 1]) == -1     # y not increasing
+    assert ws(3, 3, [0, 1, 2], [0, 1, 2], coord=4) == -1
+    assert ws(3, 3, [150, 151, 152], [10, 20, 30], coord=1) == 0
+    assert ws(3, 3, [150, 151, 152], [80, 85, 90], coord=1) == -1   # latitude out of range
+    # the message of a failure without a context is kept for the caller
+    lib.clf_last_error.restype = ctypes.c_char_p
+    lib.clf_last_error.argtypes = [ctypes.c_void_p]
+    assert ws(3, 3, [0, 1, 2], [0, 1, 1]) == -1
+    assert b"y not strictly increasing" in lib.clf_last_error(None)
