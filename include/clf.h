@@ -120,7 +120,9 @@ typedef struct clf_params {
   int32_t max_enclosed_points; /* capacity: boundary points summed over enclosed grids */
   int32_t series_capacity;  /* capacity: enclosed-grid records held */
   int32_t forcing_capacity; /* capacity: time levels per forcing side (0: no forcing) */
-  int32_t segment;          /* rows per wavefront tile of the step kernel; 0 = automatic */
+  int32_t segment;          /* rows per wavefront tile of the step kernel, 8..4096; 0 =
+                               automatic: the shortest segment whose tiles fit one wave of
+                               resident workgroups on this GPU */
   int32_t autotune;         /* 1: clf_init times candidate tile shapes on this grid and keeps
                                the fastest (cached per grid size and precision in the process) */
   int32_t graph_steps;      /* >0: step sequences that do not depend on the step index (no
