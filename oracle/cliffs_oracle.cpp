@@ -37,9 +37,11 @@
 // single-node pulse closed forms eq:u/eq:et and eq:u2/eq:et2, Lax-Wendroff
 // Fourier factor, wave speed sqrt(gH), CFL threshold, mirror symmetry,
 // transposition, 1-D reduction, wet-front advance, preprocessing
-// postcondition, restart, complex-step vs finite differences).  The
-// spherical metric terms are "parity unpinned" beyond the lake at rest and
-// the equator limit, because the paper gives no spherical equations.
+// postcondition, restart, complex-step vs finite differences).  The paper
+// gives no spherical equations; the spherical form is pinned by the lake at
+// rest, the equator limit and the first-order convergence of the
+// area-weighted volume sum(h cos(lat)), which the tan(lat) continuity source
+// decides.  The momentum equations carry no spherical terms (none pinned).
 
 #include <algorithm>
 #include <cmath>

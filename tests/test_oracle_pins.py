@@ -621,6 +621,39 @@ def test_forcing_ring(oracle_mod):
 # Spherical grid: rest is preserved; near the equator the grid reduces to a
 # Cartesian one with dx = R dlon, dy = R dlat.
 # ---------------------------------------------------------------------------
+# ---------------------------------------------------------------------------
+# Spherical continuity source (reading R10): on the sphere the continuous
+# equations conserve the area-weighted volume sum(h cos(lat)).  A zonally
+# uniform pulse travelling north and south across 10-50 N: with the tan(lat)
+# source the discrete defect shrinks at first order under refinement; without
+# it (or with a wrong sign or factor) it stays at a fixed fraction of the
+# pulse volume whatever the resolution.
+# ---------------------------------------------------------------------------
+def _sph_volume_defect(oracle_mod, N, metric):
+    lat = np.linspace(10.0, 50.0, N)
+    dl = lat[1] - lat[0]
+    lon = 150.0 + np.arange(3) * dl
+    d = np.full((N, 3), 1000.0)
+    eta = 0.01 * np.exp(-0.5 * ((lat - 30.0) / 2.0) ** 2)[:, None] * np.ones((1, 3))
+    dt = synth.cfl_dt(synth.SPHERICAL, lon, lat, d, cfl=0.8)
+    o = oracle_mod.Oracle(lon, lat, d, dt, coord=synth.SPHERICAL, ssl_alpha=0.0,
+                          spherical_metric=metric)
+    o.set_initial(eta)
+    w = np.cos(np.radians(lat))[:, None]
+    v0 = np.sum(o.raw_state()[0] * w)
+    o.step(int(round(5600.0 / dt)))     # the pulses travel about 5 degrees
+    return (np.sum(o.raw_state()[0] * w) - v0) / np.sum(eta * w)
+
+
+def test_spherical_source_conserves_area_weighted_volume(oracle_mod):
+    defects = [abs(_sph_volume_defect(oracle_mod, N, 1)) for N in (201, 401, 801)]
+    assert defects[0] / defects[1] > 1.8 and defects[1] / defects[2] > 1.8
+    assert defects[2] < 5e-5
+    # without the source the defect does not converge and is ~100x larger
+    off = [abs(_sph_volume_defect(oracle_mod, N, 0)) for N in (401, 801)]
+    assert min(off) > 1e-3 and abs(off[0] / off[1] - 1.0) < 0.05
+
+
 def test_spherical_rest_and_equator_limit(oracle_mod):
     nx, ny = 40, 30
     lon = 150.0 + np.arange(nx) * (1.0 / 600.0)
