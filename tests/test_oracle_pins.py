@@ -622,6 +622,40 @@ def test_forcing_ring(oracle_mod):
 # Cartesian one with dx = R dlon, dy = R dlat.
 # ---------------------------------------------------------------------------
 # ---------------------------------------------------------------------------
+# Wall mode (parameter items topo flag and vertical-wall depth; reading R22):
+# a node shallower than dwall never floods.  On the runup beach this equals,
+# bit for bit, inundation mode with those nodes raised to +1000 m: they differ
+# from other nodes only in the flooding test of step (b).  The unblocked run
+# floods some of them, so the equivalence is not vacuous.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dwall", [0.0, -0.05, "node"])
+def test_wall_mode_equals_raised_land(oracle_mod, dwall):
+    c = synth.beach_1d(H_over_d=0.0185, steps=900)
+    kw = dict(ssl_alpha=0.0, maxout=1)
+    free = oracle_mod.Oracle.from_case(c, itopo=1, **kw)
+    free.set_initial(c.eta0, c.u0, None)
+    free.step(c.steps)
+    if dwall == "node":
+        # exactly the depth of the second-highest land node the free run
+        # floods: the strict comparison lets that node flood
+        flooded = np.sort(c.depth[0][(free.read_maxwave()[0][0] > 0) & (c.depth[0] < 0)])
+        dwall = float(flooded[1])
+    a = oracle_mod.Oracle.from_case(c, itopo=0, dwall=dwall, **kw)
+    raised = c.depth.astype(np.float64).copy()
+    raised[raised < dwall] = -1000.0
+    b = oracle_mod.Oracle(c.x, c.y, raised, c.dt, coord=c.coord, h_min=c.h_min, itopo=1, **kw)
+    for o in (a, b):
+        o.set_initial(c.eta0, c.u0, None)
+        o.step(c.steps)
+    for x, y in zip(a.raw_state(), b.raw_state()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.read_maxwave()[0], b.read_maxwave()[0])
+    blocked = c.depth[0] < dwall
+    assert (free.read_maxwave()[0][0][blocked] > 0).any()
+    assert not (a.read_maxwave()[0][0][blocked] > 0).any()
+
+
+# ---------------------------------------------------------------------------
 # Spherical continuity source (reading R10): on the sphere the continuous
 # equations conserve the area-weighted volume sum(h cos(lat)).  A zonally
 # uniform pulse travelling north and south across 10-50 N: with the tan(lat)
