@@ -54,6 +54,8 @@ def lib():
                                      C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
             L.ora_destroy.argtypes = [C.c_void_p]
             L.ora_set_threads.argtypes = [C.c_int]
+            L.ora_cs_record_loss.argtypes = [C.c_void_p] + [_dp] * 6 + [
+                C.c_double, C.c_int, _dp, _dp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
             L.ora_ssl_passes.argtypes = [C.c_void_p]
             L.ora_max_cfl.argtypes = [C.c_void_p]
             L.ora_max_cfl.restype = C.c_double
@@ -227,6 +229,16 @@ class Oracle:
         t, vals = _f64(t), _f64(vals)
         if lib().ora_set_forcing(self._h, side, len(t), t, vals) != 0:
             raise ValueError("bad forcing")
+
+    def cs_record_loss(self, eta0, u0, v0, deta, du, dv, nsteps, obs, w=(1.0, 1.0, 1.0),
+                       h=1e-30):
+        """Weighted misfit of all gauge records (eta, u, v) and its complex-step
+        derivative along (deta, du, dv) of the initial state."""
+        L, dL = C.c_double(0), C.c_double(0)
+        lib().ora_cs_record_loss(self._h, _f64(eta0), _f64(u0), _f64(v0), _f64(deta), _f64(du),
+                                 _f64(dv), h, int(nsteps), _f64(obs), _f64(np.asarray(w)),
+                                 C.byref(L), C.byref(dL))
+        return L.value, dL.value
 
     def cs_gauge_loss(self, eta0, deta, nsteps, obs, h=1e-30):
         L, dL = C.c_double(0), C.c_double(0)

@@ -989,4 +989,43 @@ int ora_cs_gauge_loss(void* h, const double* eta, const double* deta, double hst
   return (int)nrec;
 }
 
+// Complex-step derivative of a weighted misfit of every gauge record,
+//   L = sum over records q, gauges g, components c of 0.5 w_c (rec - obs)^2
+// with components (eta, u, v), along a direction (deta, du, dv) of the
+// initial surface (free-surface deformation) and velocities.  Velocities of
+// dry nodes are zero, as after any initial condition.  obs: [nrec][ng][3].
+int ora_cs_record_loss(void* h, const double* eta, const double* u, const double* v,
+                       const double* deta, const double* du, const double* dv, double hstep,
+                       int nsteps, const double* obs, const double* w, double* L, double* dL) {
+  OraModel* r = (OraModel*)h;
+  Model<cplx> m;
+  m.nx = r->nx; m.ny = r->ny; m.coord = r->coord;
+  m.x = r->x; m.y = r->y; m.d = r->d; m.p = r->p;
+  m.xfac = r->xfac; m.xib = r->xib; m.xisb = r->xisb;
+  m.yib = r->yib; m.yisb = r->yisb; m.tanR = r->tanR;
+  m.gx = r->gx; m.gy = r->gy;
+  const size_t N = (size_t)m.nx * m.ny;
+  m.H.assign(N, cplx(0.0)); m.u.assign(N, cplx(0.0)); m.v.assign(N, cplx(0.0));
+  std::vector<cplx> e(N);
+  for (size_t k = 0; k < N; ++k) e[k] = cplx(eta[k], hstep * deta[k]);
+  set_initial_t(m, nullptr, e.data(), nullptr, nullptr, 0);
+  for (size_t k = 0; k < N; ++k)
+    if (re(m.H[k]) > 0.0) {  // wet after the dry pass (dry nodes hold h = 0)
+      m.u[k] = cplx(u[k], hstep * du[k]);
+      m.v[k] = cplx(v[k], hstep * dv[k]);
+    }
+  for (int s = 0; s < nsteps; ++s) step_once(m);
+  const size_t nrec = m.gtime.size(), ng = m.gx.size();
+  cplx acc(0.0);
+  for (size_t q = 0; q < nrec; ++q)
+    for (size_t g = 0; g < ng; ++g)
+      for (int c = 0; c < 3; ++c) {
+        cplx dvv = m.grec[(q * ng + g) * 3 + c] - obs[(q * ng + g) * 3 + c];
+        acc += 0.5 * w[c] * dvv * dvv;
+      }
+  *L = acc.real();
+  *dL = acc.imag() / hstep;
+  return (int)nrec;
+}
+
 }  // extern "C"

@@ -57,6 +57,35 @@ def test_adjoint_dot_product_vs_complex_step(clf, oracle_mod, land):
         assert abs(ad - dL) <= 1e-9 * max(abs(dL), 1e-30) + 1e-14
 
 
+@pytest.mark.parametrize("land", [False, True], ids=["wet", "land"])
+def test_adjoint_all_components_vs_complex_step(clf, oracle_mod, land):
+    # gradients with respect to the initial surface and both velocities, for
+    # a weighted misfit of every record component (eta, u, v): the u / v
+    # record adjoints and the velocity gradients of the initial condition
+    c = synth.random_small(70 + int(land), 64, 50, land=land, amp=0.3)
+    nsteps = 30
+    gx = np.array([6, 30, 55, 41]); gy = np.array([8, 26, 40, 12])
+    s = clf.Solver.from_case(c, gout=3)
+    s.set_gauges(gx, gy)
+    o = oracle_mod.Oracle.from_case(c, gout=3)
+    o.set_gauges(gx, gy)
+    rng = np.random.default_rng(13)
+    obs = 0.05 * rng.standard_normal((nsteps // 3 + 1, len(gx), 3))
+    w = np.array([1.0, 0.3, 2.0])
+    s.set_initial(c.eta0, c.u0, c.v0)
+    s.adjoint_forward(nsteps, 0)
+    rec = s.read_gauges()[0]
+    ge, gu, gv = (t.cpu().numpy() for t in s.adjoint_backward(w[None, None, :] * (rec - obs)))
+    for trial in range(2):
+        d = [rng.standard_normal(c.eta0.shape) for _ in range(3)]
+        Lo, dL = o.cs_record_loss(c.eta0, c.u0, c.v0, d[0], d[1], d[2], nsteps, obs, w)
+        L = 0.5 * float(np.sum(w[None, None, :] * (rec - obs) ** 2))
+        assert abs(Lo - L) <= 1e-12 * abs(L)
+        ad = float(np.sum(ge * d[0]) + np.sum(gu * d[1]) + np.sum(gv * d[2]))
+        print("all components", "land" if land else "wet", trial, ad, dL)
+        assert abs(ad - dL) <= 1e-9 * max(abs(dL), 1e-30) + 1e-14
+
+
 @pytest.mark.parametrize("variant", ["spherical", "solver1", "friction"])
 def test_adjoint_variants_vs_complex_step(clf, oracle_mod, variant):
     # the reverse-mode interior path and the shoreline path under the

@@ -741,6 +741,33 @@ def test_complex_step_matches_finite_differences(oracle_mod):
     assert abs(fd - dL) <= 1e-6 * abs(dL)
 
 
+def test_complex_step_all_records_matches_finite_differences(oracle_mod):
+    # the weighted misfit of all record components (eta, u, v) along a
+    # direction of the initial surface and velocities
+    c = synth.random_small(31, 24, 20, land=False, amp=0.2)
+    o = oracle_mod.Oracle.from_case(c, gout=2)
+    gx = np.array([3, 10, 17]); gy = np.array([4, 12, 15])
+    o.set_gauges(gx, gy)
+    nsteps = 24
+    rng = np.random.default_rng(5)
+    obs = 0.01 * rng.standard_normal((nsteps // 2 + 1, 3, 3))
+    w = np.array([1.0, 0.3, 2.0])
+    d = [rng.standard_normal(c.eta0.shape) * s for s in (0.01, 0.01, 0.01)]
+
+    def loss(eta, u, v):
+        o.set_initial(eta, u, v)
+        o.step(nsteps)
+        rec, _ = o.read_gauges()
+        return 0.5 * np.sum(w[None, None, :] * (rec - obs) ** 2)
+
+    L, dL = o.cs_record_loss(c.eta0, c.u0, c.v0, d[0], d[1], d[2], nsteps, obs, w)
+    assert abs(L - loss(c.eta0, c.u0, c.v0)) <= 1e-13 * abs(L)
+    h = 1e-4
+    fd = (loss(c.eta0 + h * d[0], c.u0 + h * d[1], c.v0 + h * d[2]) -
+          loss(c.eta0 - h * d[0], c.u0 - h * d[1], c.v0 - h * d[2])) / (2 * h)
+    assert abs(fd - dL) <= 1e-6 * abs(dL)
+
+
 # ---------------------------------------------------------------------------
 # Mass: the characteristic-form scheme is not conservative; the relative
 # defect shrinks under refinement (first order or better).
