@@ -1,8 +1,9 @@
 """Differentiable gauge records for source inversion.
 
-``GaugeRecords.apply(eta0, solver, nsteps, ckpt_every)`` runs the split step
-from the initial surface eta0 (a free-surface deformation) and returns the
-gauge records [nrec][ng][3] (eta, u, v) as a tensor.  Its backward pass is the
+``GaugeRecords.apply(eta0, solver, nsteps, ckpt_every, u0, v0)`` runs the
+split step from the initial surface eta0 (a free-surface deformation) and
+velocities u0, v0 (optional; None = at rest) and returns the gauge records
+[nrec][ng][3] (eta, u, v) as a tensor.  Its backward pass is the
 library's adjoint (clf_adjoint_backward): frozen wet/dry decisions, a
 checkpoint every ckpt_every steps (0: ceil(sqrt(nsteps))).  The map from
 source coefficients to eta0 is ordinary torch (a linear combination of unit
@@ -15,17 +16,21 @@ import torch
 
 class GaugeRecords(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, eta0, solver, nsteps, ckpt_every=0):
-        solver.set_initial(eta0.detach())
+    def forward(ctx, eta0, solver, nsteps, ckpt_every=0, u0=None, v0=None):
+        solver.set_initial(eta0.detach(), None if u0 is None else u0.detach(),
+                           None if v0 is None else v0.detach())
         solver.adjoint_forward(int(nsteps), int(ckpt_every))
         rec, _ = solver.read_gauges()
         ctx.solver = solver
+        ctx.has_uv = (u0 is not None, v0 is not None)
         return torch.from_numpy(rec).to(device=eta0.device, dtype=eta0.dtype)
 
     @staticmethod
     def backward(ctx, grad_rec):
-        d_eta0, _, _ = ctx.solver.adjoint_backward(grad_rec.detach().double().cpu().numpy())
-        return d_eta0, None, None, None
+        d_eta0, d_u0, d_v0 = ctx.solver.adjoint_backward(
+            grad_rec.detach().double().cpu().numpy())
+        return (d_eta0, None, None, None, d_u0 if ctx.has_uv[0] else None,
+                d_v0 if ctx.has_uv[1] else None)
 
 
 def unit_sources_to_eta(coeffs, basis):

@@ -168,3 +168,17 @@ def test_autograd_function(clf):
     L, g_eta = misfit_grad(s, np.tensordot(c0, basis, axes=1), 100, 0.0)
     g = np.tensordot(basis, g_eta, axes=([1, 2], [0, 1]))
     assert np.allclose(c.grad.cpu().numpy(), g, rtol=1e-12, atol=0)
+    # velocities as leaves too, with a misfit on every record component:
+    # the same gradients as the direct adjoint call
+    u0 = torch.full(B.shape[1:], 0.05, dtype=torch.float64, device="cuda", requires_grad=True)
+    v0 = torch.full(B.shape[1:], -0.02, dtype=torch.float64, device="cuda", requires_grad=True)
+    eta = unit_sources_to_eta(torch.tensor(c0, device="cuda"), B)
+    rec = GaugeRecords.apply(eta, s, 100, 0, u0, v0)
+    (0.5 * (rec ** 2).sum()).backward()
+    s.set_initial(eta, u0.detach(), v0.detach())
+    s.adjoint_forward(100, 0)
+    r = s.read_gauges()[0]
+    ge, gu, gv = s.adjoint_backward(r)
+    assert torch.allclose(u0.grad, gu, rtol=1e-12, atol=0)
+    assert torch.allclose(v0.grad, gv, rtol=1e-12, atol=0)
+    assert float(gu.abs().max()) > 0 and float(gv.abs().max()) > 0
