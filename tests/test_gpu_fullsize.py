@@ -109,3 +109,57 @@ def test_full_length_runs_stay_finite(clf, wl):
         print("  max speed %.3f max |eta| %.3f" % (smax, emax), flush=True)
         assert smax < 50.0 and emax < 50.0
         del g
+
+
+def test_full_size_8000x6000_fp64_with_friction(clf, oracle_mod):
+    # the FP64 runup grid as bench.py runs it (friction, autotuned segment,
+    # gauges, maxwave) against the oracle: friction is held to 1e-10
+    case = synth.config5(steps=3)
+    print("full-size 8000x6000 FP64, 3 steps", flush=True)
+    g = clf.Solver.from_case(case, gout=10, maxout=1, autotune=1)
+    g.set_initial(case.eta0, case.u0, case.v0)
+    g.step(3)
+    hg, ug, vg = (t.cpu().numpy() for t in g.raw_state())
+    del g
+    o = oracle_mod.Oracle.from_case(case, gout=10, maxout=1)
+    o.set_initial(case.eta0, case.u0, case.v0)
+    o.step(3)
+    ho, uo, vo = o.raw_state()
+    for a, b, name in ((hg, ho, "h"), (ug, uo, "u"), (vg, vo, "v")):
+        scale = max(np.abs(b).max(), 1e-300)
+        err = np.abs(a - b).max() / scale
+        print(name, "max rel", err)
+        assert err <= 1e-10
+    assert np.array_equal(hg > case.h_min, ho > case.h_min)
+
+
+def test_full_size_ensemble_64_members(clf, oracle_mod):
+    # the 64-member FP32 ensemble in bench.py's launch configuration: every
+    # member equals its single-grid run bit for bit; three members of the
+    # FP64 ensemble equal the oracle bit for bit
+    cases = synth.config3(n=64, steps=12)
+    print("full-size ensemble, 64 members, 12 steps", flush=True)
+    ens = clf.Ensemble(cases, precision=clf.FP32, maxout=1, autotune=1)
+    for i, c in enumerate(cases):
+        ens.set_initial(i, c.eta0, c.u0, c.v0)
+    ens.step(12)
+    for i, c in enumerate(cases):
+        s = clf.Solver.from_case(c, precision=clf.FP32, maxout=1)
+        s.set_initial(c.eta0, c.u0, c.v0)
+        s.step(12)
+        for a, b in zip(ens.state(i), s.state()):
+            assert np.array_equal(a.cpu().numpy(), b.cpu().numpy()), "member %d" % i
+        del s
+    del ens
+    e64 = clf.Ensemble(cases, precision=clf.FP64, maxout=1, autotune=1)
+    for i, c in enumerate(cases):
+        e64.set_initial(i, c.eta0, c.u0, c.v0)
+    e64.step(12)
+    for i in (0, 31, 63):
+        o = oracle_mod.Oracle.from_case(cases[i], maxout=1)
+        o.set_initial(cases[i].eta0, cases[i].u0, cases[i].v0)
+        o.step(12)
+        eo, uo, vo, wo = o.state()
+        eg, ug, vg, wg = (t.cpu().numpy() for t in e64.state(i))
+        assert np.array_equal(eg, eo) and np.array_equal(ug, uo) and np.array_equal(vg, vo)
+        assert np.array_equal(wg, wo)
