@@ -12,6 +12,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -25,6 +27,43 @@
 #include <vector>
 
 using namespace clf;
+
+namespace {
+
+// Host trace ranges (roctx) around the library's calls, seen by a profiler
+// (rocprofv3 --marker-trace).  The roctx library is looked up once at run
+// time; without it the ranges cost nothing and the library has no link-time
+// dependency on it.
+struct Roctx {
+  int (*push)(const char*) = nullptr;
+  int (*pop)() = nullptr;
+};
+
+const Roctx& roctx() {
+  static Roctx r = [] {
+    Roctx t;
+    void* h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (!h) h = dlopen("libroctx64.so.4", RTLD_NOW | RTLD_LOCAL);
+    if (h) {
+      t.push = (int (*)(const char*))dlsym(h, "roctxRangePushA");
+      t.pop = (int (*)())dlsym(h, "roctxRangePop");
+      if (!t.push || !t.pop) t.push = nullptr, t.pop = nullptr;
+    }
+    return t;
+  }();
+  return r;
+}
+
+struct TraceRange {
+  explicit TraceRange(const char* name) {
+    if (roctx().push) roctx().push(name);
+  }
+  ~TraceRange() {
+    if (roctx().pop) roctx().pop();
+  }
+};
+
+}  // namespace
 
 namespace {
 
@@ -766,6 +805,7 @@ static int ctx_create(clf_ctx** out, const clf_grid* g, const double* depth, dou
 
 int clf_init(clf_ctx** out, const clf_grid* g, const double* depth, double dt,
              const clf_params* p, void* stream, void* ws, size_t ws_bytes) {
+  TraceRange trace_("clf_init");
   return ctx_create(out, g, depth, dt, p, stream, ws, ws_bytes, true);
 }
 
@@ -989,6 +1029,7 @@ static int step_order(clf_ctx* c) {
 }
 
 int clf_step(clf_ctx* c, int nsteps) {
+  TraceRange trace_("clf_step");
   int rc = check_ready(c);
   if (rc) return rc;
   if (nsteps < 0) return fail(c, CLF_EINVAL, "negative step count");
@@ -1255,6 +1296,7 @@ int clf_adjoint_workspace_bytes(const clf_ctx* c, int nsteps, int ckpt_every, si
 }
 
 int clf_adjoint_forward(clf_ctx* c, int nsteps, int ckpt_every, void* ws, size_t ws_bytes) {
+  TraceRange trace_("clf_adjoint_forward");
   int rc = check_ready(c);
   if (rc) return rc;
   if (c->fp32) return fail(c, CLF_EINVAL, "the adjoint needs an FP64 context");
@@ -1307,6 +1349,7 @@ int clf_adjoint_forward(clf_ctx* c, int nsteps, int ckpt_every, void* ws, size_t
 
 int clf_adjoint_backward(clf_ctx* c, const double* rec_adj, int nrec, double* d_eta0,
                          double* d_u0, double* d_v0) {
+  TraceRange trace_("clf_adjoint_backward");
   int rc = check_ready(c);
   if (rc) return rc;
   if (!c->adj_ready) return fail(c, CLF_ESTATE, "no adjoint forward run to reverse");
@@ -1650,6 +1693,7 @@ int clf_ensemble_set_initial(clf_ens* e, int member, const double* eta, const do
 }
 
 int clf_ensemble_step(clf_ens* e, int nsteps) {
+  TraceRange trace_("clf_ensemble_step");
   if (!e) return CLF_EINVAL;
   if (nsteps < 0) return efail(e, CLF_EINVAL, "negative step count");
   const int nb = eff_blocks(e->nblocks, e->p.persistent_blocks);
