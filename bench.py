@@ -495,15 +495,16 @@ def main():
         rb["workload"] = big.name + (" (fp64, 50 gauges every 10 steps, maxwave every step, "
                                      "4 enclosed-grid boundary series every step)")
         extras["large_grid_fp64"] = rb
+        if not args.no_cpu:
+            log("oracle on the other workloads ...")
+            extras["cpu_other"] = cpu_other([("200x200", synth.config1(steps=10), 400),
+                                             ("8000x6000", big, 2)])
         del big
         log("ensemble ...")
         extras["ensemble"] = run_ensemble(min(args.steps, 300))
         log("adjoint ...")
         extras["adjoint"] = run_adjoint(3000, cpu_fd=not args.no_cpu)
-        if not args.no_cpu:
-            log("oracle on the other workloads ...")
-            extras["cpu_other"] = cpu_other([("200x200", synth.config1(steps=10), 400),
-                                             ("8000x6000", synth.config5(steps=10), 2)])
+
         out["extras"] = extras
     print(json.dumps(out), flush=True)
 
