@@ -177,9 +177,9 @@ struct P64 {
     return (f & F_EX) && !(f & (F_WET | F_FIX)) && (((fl & ew) == ew) || ((fr & ew) == ew));
   }
 
-  static __device__ __forceinline__ void set_c(B& b) {
-    b.c = (b.f & F_WET) ? sqrt(kG * b.H) : 0.0;
-  }
+  // c = sqrt(g h) on every node: dry nodes hold h = 0 (so c = 0), and c of
+  // a node outside the grid is never used (it is no real neighbour)
+  static __device__ __forceinline__ void set_c(B& b) { b.c = sqrt(kG * b.H); }
 
   static __device__ __forceinline__ Bx bx(const B& b) {
     Bx x;
@@ -403,9 +403,7 @@ struct P32 {
     return (f & F_EX) && !(f & (F_WET | F_FIX)) && (((fl & ew) == ew) || ((fr & ew) == ew));
   }
 
-  static __device__ __forceinline__ void set_c(B& b) {
-    b.c = (b.f & F_WET) ? __builtin_amdgcn_sqrtf(kGf * b.h) : 0.f;
-  }
+  static __device__ __forceinline__ void set_c(B& b) { b.c = __builtin_amdgcn_sqrtf(kGf * b.h); }
 
   static __device__ __forceinline__ Bx bx(const B& b) {
     Bx x;
@@ -740,7 +738,8 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
       gstore(cx.Ho + k, o.H);
       gstore(cx.Uo + k, o.w);
       gstore(cx.Vo + k, o.t);
-      if (!(isfinite(o.H) && isfinite(o.w) && isfinite(o.t))) bad = 1;
+      // one test: a NaN or an infinity in any term makes the sum non-finite
+      if (!isfinite((o.H + o.w) + o.t)) bad = 1;
       if (do_max && P::wet_out(o, D, cx.par)) {
         R e = P::eta_out(o, D);
         if (e > m.e) gstore(cx.emax + k, e);
