@@ -13,6 +13,12 @@
 //     D = step (e).  Each stage needs its neighbours one row up and down, so
 //     the row leaving the pipeline lags the row entering it by 3 and a
 //     segment re-reads 3 rows above and below it.
+// The eqQ value of an interface is the same bits for the two nodes it
+// separates when both are wet, so each sweep evaluates it once, on the node
+// above or left of it, and hands it on: across lanes in the x-sweep, in a
+// register down the y pipeline.  Selecting its operands first (the real
+// neighbour, or the node's own mirror ghost) covers the wall cases with the
+// same single evaluation.
 // Every node of the state is read once and written once per step (plus the
 // depth and the maxwave read-modify-write); rows are read with fully
 // coalesced loads along x.  There is no LDS and no barrier.
@@ -119,13 +125,14 @@ struct P64 {
   };
 
   static __device__ __forceinline__ void stage_a(A& a, const Par& p) {
-    if (a.f & F_EX) {
-      if (a.H > p.hmin) {
-        a.f |= F_WET;
-      } else {
-        a.H = 0.0; a.w = 0.0; a.t = 0.0;
-      }
-    }
+    // branch-free: a node in the grid at or below the threshold is emptied
+    const bool ex = (a.f & F_EX) != 0;
+    const bool wet = a.H > p.hmin;
+    const bool dry = ex && !wet;
+    a.f |= (ex && wet) ? F_WET : 0;
+    a.H = dry ? 0.0 : a.H;
+    a.w = dry ? 0.0 : a.w;
+    a.t = dry ? 0.0 : a.t;
   }
 
   static __device__ __forceinline__ B stage_b(const A& l, const A& c, const A& r, const Par& p) {
@@ -226,10 +233,44 @@ struct P64 {
     return a3 + b4;
   }
 
+  // eqQ across the interface a|b for the P, M and T families.  Between two
+  // real wet nodes the value is the same bits whichever node evaluates it
+  // (the sums are taken b + a in both), so a sweep computes it once per
+  // interface and hands it to the node on the other side.
+  struct Fx { double P, M, T; };
+  static __device__ __forceinline__ Fx flux(double wa, double ca, double Da, double ta,
+                                            double wb, double cb, double Db, double tb,
+                                            double inv) {
+    Fx f;
+    f.P = qhat(wa + ca, wa + 2.0 * ca, Da, wb + cb, wb + 2.0 * cb, Db, inv);
+    f.M = qhat(wa - ca, wa - 2.0 * ca, Da, wb - cb, wb - 2.0 * cb, Db, inv);
+    f.T = qhat_t(wa, ta, wb, tb, inv);
+    return f;
+  }
+  // The value an interface a|b must have for whichever of its two nodes is
+  // real (inside the grid and wet after (b)): with both real it is eqQ over
+  // a and b; with one real, eqQ between that node and its own mirror ghost
+  // (h, -w, t, d).  Selecting the operands first gives all three cases from
+  // one evaluation; with neither real the value is never used.
+  static __device__ __forceinline__ Fx interface(const B& a, bool areal, const Bx& b, bool breal,
+                                                 double inv) {
+    const double aw = areal ? a.w : -b.w, ac = areal ? a.c : b.c, aD = areal ? a.D : b.D,
+                 at = areal ? a.t : b.t;
+    const double bw = breal ? b.w : -a.w, bc = breal ? b.c : a.c, bD = breal ? b.D : a.D,
+                 bt = breal ? b.t : a.t;
+    return flux(aw, ac, aD, at, bw, bc, bD, bt, inv);
+  }
+
+  // (d) from the values of the interfaces on each side of the node
+  static __device__ __forceinline__ C stage_cd_shared(const B& c, const Fx& FL, const Fx& FR,
+                                                      double iS, double tanR, const Par& p) {
+    return finish(c, FL.P, FR.P, FL.M, FR.M, FL.T, FR.T, 0.0, 0.0, 0.0, iS, tanR, p);
+  }
+
+  // (d) with every neighbour evaluated in place (needed by solver1, whose
+  // centred term spans both neighbours)
   static __device__ __forceinline__ C stage_cd(const Bx& l, const B& c, const Bx& r, double iL,
                                                double iR, double iS, double tanR, const Par& p) {
-    // Every lane computes the update; dry and held nodes select their value
-    // at the end (a wet node's result is the same bits either way).
     const bool lreal = (l.f & (F_EX | F_WET)) == (F_EX | F_WET);
     const bool rreal = (r.f & (F_EX | F_WET)) == (F_EX | F_WET);
     const double Cw = c.w, Ct = c.t, CD = c.D, Cc = c.c;
@@ -238,22 +279,24 @@ struct P64 {
                  Lc = lreal ? l.c : Cc;
     const double Rw = rreal ? r.w : -Cw, Rt = rreal ? r.t : Ct, RD = rreal ? r.D : CD,
                  Rc = rreal ? r.c : Cc;
-    double xPL = Lw + 2.0 * Lc, xPC = Cw + 2.0 * Cc, xPR = Rw + 2.0 * Rc;
-    double lPL = Lw + Lc, lPC = Cw + Cc, lPR = Rw + Rc;
-    double xML = Lw - 2.0 * Lc, xMC = Cw - 2.0 * Cc, xMR = Rw - 2.0 * Rc;
-    double lML = Lw - Lc, lMC = Cw - Cc, lMR = Rw - Rc;
-    double QPL = qhat(lPL, xPL, LD, lPC, xPC, CD, iL);
-    double QPR = qhat(lPC, xPC, CD, lPR, xPR, RD, iR);
-    double QML = qhat(lML, xML, LD, lMC, xMC, CD, iL);
-    double QMR = qhat(lMC, xMC, CD, lMR, xMR, RD, iR);
-    double QTL = qhat_t(Lw, Lt, Cw, Ct, iL);
-    double QTR = qhat_t(Cw, Ct, Rw, Rt, iR);
+    const Fx QL = flux(Lw, Lc, LD, Lt, Cw, Cc, CD, Ct, iL);
+    const Fx QR = flux(Cw, Cc, CD, Ct, Rw, Rc, RD, Rt, iR);
     double QPc = 0.0, QMc = 0.0, QTc = 0.0;
     if (p.flags & G_SOLVER1) {
-      QPc = qhat(lPL, xPL, LD, lPR, xPR, RD, iS);
-      QMc = qhat(lML, xML, LD, lMR, xMR, RD, iS);
-      QTc = qhat_t(Lw, Lt, Rw, Rt, iS);
+      const Fx Qc = flux(Lw, Lc, LD, Lt, Rw, Rc, RD, Rt, iS);
+      QPc = Qc.P; QMc = Qc.M; QTc = Qc.T;
     }
+    return finish(c, QL.P, QR.P, QL.M, QR.M, QL.T, QR.T, QPc, QMc, QTc, iS, tanR, p);
+  }
+
+  static __device__ __forceinline__ C finish(const B& c, double QPL, double QPR, double QML,
+                                             double QMR, double QTL, double QTR, double QPc,
+                                             double QMc, double QTc, double iS, double tanR,
+                                             const Par& p) {
+    // Every lane computes the update; dry and held nodes select their value
+    // at the end (a wet node's result is the same bits either way).
+    const double Cw = c.w, Ct = c.t, Cc = c.c;
+    const double xPC = Cw + 2.0 * Cc, lPC = Cw + Cc, xMC = Cw - 2.0 * Cc, lMC = Cw - Cc;
     double Pn = advance(p, xPC, lPC, QPL, QPR, QPc, iS);
     double Mn = advance(p, xMC, lMC, QML, QMR, QMc, iS);
     double Tn = advance(p, Ct, Cw, QTL, QTR, QTc, iS);
@@ -344,13 +387,13 @@ struct P32 {
   };
 
   static __device__ __forceinline__ void stage_a(A& a, const Par& p) {
-    if (a.f & F_EX) {
-      if (a.D + a.H > p.hmin) {
-        a.f |= F_WET;
-      } else {
-        a.H = -a.D; a.w = 0.f; a.t = 0.f;
-      }
-    }
+    const bool ex = (a.f & F_EX) != 0;
+    const bool wet = a.D + a.H > p.hmin;
+    const bool dry = ex && !wet;
+    a.f |= (ex && wet) ? F_WET : 0;
+    a.H = dry ? -a.D : a.H;
+    a.w = dry ? 0.f : a.w;
+    a.t = dry ? 0.f : a.t;
   }
 
   static __device__ __forceinline__ B stage_b(const A& l, const A& c, const A& r, const Par& p) {
@@ -435,6 +478,32 @@ struct P32 {
     return first + ((lam * p.dt2) * (QR - QL)) * iS;
   }
 
+  // the interface values of the three families (shared between the two
+  // nodes of a real wet interface, as in the FP64 stages)
+  struct Fx { float P, M, T; };
+  static __device__ __forceinline__ Fx flux(float wa, float ca, float ea, float Da, float ta,
+                                            float wb, float cb, float eb, float Db, float tb,
+                                            float inv) {
+    Fx f;
+    f.P = qpm(1.f, wa, ca, ea, Da, wb, cb, eb, Db, inv);
+    f.M = qpm(-1.f, wa, ca, ea, Da, wb, cb, eb, Db, inv);
+    f.T = qt(wa, ta, wb, tb, inv);
+    return f;
+  }
+  static __device__ __forceinline__ Fx interface(const B& a, bool areal, const Bx& b, bool breal,
+                                                 float inv) {
+    const float aw = areal ? a.w : -b.w, ac = areal ? a.c : b.c, ae = areal ? a.H : b.H,
+                aD = areal ? a.D : b.D, at = areal ? a.t : b.t;
+    const float bw = breal ? b.w : -a.w, bc = breal ? b.c : a.c, be = breal ? b.H : a.H,
+                bD = breal ? b.D : a.D, bt = breal ? b.t : a.t;
+    return flux(aw, ac, ae, aD, at, bw, bc, be, bD, bt, inv);
+  }
+
+  static __device__ __forceinline__ C stage_cd_shared(const B& c, const Fx& FL, const Fx& FR,
+                                                      float iS, float tanR, const Par& p) {
+    return finish(c, FL.P, FR.P, FL.M, FR.M, FL.T, FR.T, 0.f, 0.f, 0.f, iS, tanR, p);
+  }
+
   static __device__ __forceinline__ C stage_cd(const Bx& l, const B& c, const Bx& r, float iL,
                                                float iR, float iS, float tanR, const Par& p) {
     const bool lreal = (l.f & (F_EX | F_WET)) == (F_EX | F_WET);
@@ -445,18 +514,21 @@ struct P32 {
                 Lc = lreal ? l.c : Cc, Le = lreal ? l.H : Ce;
     const float Rw = rreal ? r.w : -Cw, Rt = rreal ? r.t : Ct, RD = rreal ? r.D : CD,
                 Rc = rreal ? r.c : Cc, Re = rreal ? r.H : Ce;
-    const float QPL = qpm(1.f, Lw, Lc, Le, LD, Cw, Cc, Ce, CD, iL);
-    const float QPR = qpm(1.f, Cw, Cc, Ce, CD, Rw, Rc, Re, RD, iR);
-    const float QML = qpm(-1.f, Lw, Lc, Le, LD, Cw, Cc, Ce, CD, iL);
-    const float QMR = qpm(-1.f, Cw, Cc, Ce, CD, Rw, Rc, Re, RD, iR);
-    const float QTL = qt(Lw, Lt, Cw, Ct, iL);
-    const float QTR = qt(Cw, Ct, Rw, Rt, iR);
+    const Fx QL = flux(Lw, Lc, Le, LD, Lt, Cw, Cc, Ce, CD, Ct, iL);
+    const Fx QR = flux(Cw, Cc, Ce, CD, Ct, Rw, Rc, Re, RD, Rt, iR);
     float QPc = 0.f, QMc = 0.f, QTc = 0.f;
     if (p.flags & G_SOLVER1) {
-      QPc = qpm(1.f, Lw, Lc, Le, LD, Rw, Rc, Re, RD, iS);
-      QMc = qpm(-1.f, Lw, Lc, Le, LD, Rw, Rc, Re, RD, iS);
-      QTc = qt(Lw, Lt, Rw, Rt, iS);
+      const Fx Qc = flux(Lw, Lc, Le, LD, Lt, Rw, Rc, Re, RD, Rt, iS);
+      QPc = Qc.P; QMc = Qc.M; QTc = Qc.T;
     }
+    return finish(c, QL.P, QR.P, QL.M, QR.M, QL.T, QR.T, QPc, QMc, QTc, iS, tanR, p);
+  }
+
+  static __device__ __forceinline__ C finish(const B& c, float QPL, float QPR, float QML,
+                                             float QMR, float QTL, float QTR, float QPc,
+                                             float QMc, float QTc, float iS, float tanR,
+                                             const Par& p) {
+    const float Cw = c.w, Ct = c.t, CD = c.D, Cc = c.c, Ce = c.H;
     float dP = incr(p, Cw + Cc, QPL, QPR, QPc, iS);
     float dM = incr(p, Cw - Cc, QML, QMR, QMc, iS);
     const float dT = incr(p, Cw, QTL, QTR, QTc, iS);
@@ -544,6 +616,10 @@ __device__ __forceinline__ int ring_flag(int gflags, int xc, int r, int nx, int 
              : 0;
 }
 
+// a neighbour that takes part in (d) with its own values: inside the grid
+// and wet after (b); any other neighbour is replaced by the mirror ghost
+__device__ __forceinline__ bool is_real(int f) { return (f & (F_EX | F_WET)) == (F_EX | F_WET); }
+
 // x-sweep of one row across the wavefront.  In: this lane's node along x
 // (w = u, t = v), unflagged wet state.  Out: post-sweep (H, u, v), valid on
 // lanes 3..60.  The flooding exchange of step (b) and the limiter exchange
@@ -567,9 +643,17 @@ __device__ __forceinline__ typename P::C xsweep_row(typename P::A a, typename P:
   }
   P::set_c(b);
   typename P::Bx bx = P::bx(b);
-  typename P::Bx bl = from_prev(bx);
   typename P::Bx br = from_next(bx);
-  C c = P::stage_cd(bl, b, br, iL, iR, iS, (typename P::R)0, par);
+  C c;
+  if (par.flags & G_SOLVER1) {
+    typename P::Bx bl = from_prev(bx);
+    c = P::stage_cd(bl, b, br, iL, iR, iS, (typename P::R)0, par);
+  } else {
+    // each lane evaluates the interface to its right and passes it on
+    const typename P::Fx FR = P::interface(b, is_real(b.f), br, is_real(br.f), iR);
+    const typename P::Fx FL = from_prev(FR);
+    c = P::stage_cd_shared(b, FL, FR, iS, (typename P::R)0, par);
+  }
   if (__ballot(b.src != 0) != 0) {
     typename P::Cx cc = P::cx(c);
     typename P::Cx cl = from_prev(cc);
@@ -585,11 +669,13 @@ __device__ __forceinline__ typename P::C xsweep_row(typename P::A a, typename P:
 //   a[(K+1)%3], a[(K+2)%3], a[K] = post-(a) rows r-2, r-1, r
 //   b[(K+1)%3], b[(K+2)%3], b[K] = post-(b) rows r-3, r-2, r-1
 //   c[(K+1)%3], c[(K+2)%3], c[K] = post-(d) rows r-4, r-3, r-2
+//   F[K] = interface values between rows r-2 and r-1
 template <class P>
 struct YPipe {
   typename P::A a[3];
   typename P::B b[3];
   typename P::C c[3];
+  typename P::Fx F[3];
 
   __device__ __forceinline__ void reset() {
 #pragma unroll
@@ -597,15 +683,17 @@ struct YPipe {
       a[k] = typename P::A{};
       b[k] = typename P::B{};
       c[k] = typename P::C{};
+      F[k] = typename P::Fx{};
     }
   }
 };
 
 // Push row r (y view: w = v, t = u) in phase K; returns the final state of
 // row r-3 in `out` and its post-(b) view (flags, depth, flood source) in `ob`.
-template <class P, int K>
+// y0 is the first row the segment writes.
+template <class P, int K, bool SH>
 __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_in, int r,
-                                           const Ctx<P>& cx, typename P::C& out,
+                                           int y0, const Ctx<P>& cx, typename P::C& out,
                                            typename P::B& ob) {
   typedef typename P::R R;
   constexpr int K1 = (K + 1) % 3, K2 = (K + 2) % 3;
@@ -623,11 +711,27 @@ __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_i
   R iL = 1, iR = 1, iS = 1, tr = 0;
   if (rc >= 0 && rc < cx.ny) {
     iL = cload(cx.yib + rc);
-    iR = cload(cx.yib + rc + 1);
     iS = cload(cx.yisb + rc);
     if (cx.par.flags & G_SPHSRC) tr = cload(cx.tanR + rc);
   }
-  y.c[K] = P::stage_cd(P::bx(y.b[K1]), y.b[K2], P::bx(y.b[K]), iL, iR, iS, tr, cx.par);
+  // the interface below row rc is also that above row rc + 1, so its
+  // spacing is needed from row -1 on (the edge interface of row 0)
+  if (rc >= -1 && rc < cx.ny) iR = cload(cx.yib + rc + 1);
+  if (!SH || (cx.par.flags & G_SOLVER1)) {
+    y.c[K] = P::stage_cd(P::bx(y.b[K1]), y.b[K2], P::bx(y.b[K]), iL, iR, iS, tr, cx.par);
+  } else {
+    // the interface above row r-2 was evaluated by the previous push (as the
+    // one below row r-3); evaluate the one below and keep it for the next.
+    // Rows above y0 - 1 only feed rows above the segment, so their update is
+    // skipped (a uniform branch), and of row y0 - 2 only the interface below
+    // it is kept.
+    if (rc >= y0 - 2) {
+      const typename P::Fx FR =
+          P::interface(y.b[K2], is_real(y.b[K2].f), P::bx(y.b[K]), is_real(y.b[K].f), iR);
+      if (rc >= y0 - 1) y.c[K] = P::stage_cd_shared(y.b[K2], y.F[K2], FR, iS, tr, cx.par);
+      y.F[K] = FR;
+    }
+  }
   // (e) on row r-3
   out = y.c[K2];
   ob = y.b[K1];
@@ -641,18 +745,19 @@ constexpr int FL_FRIC = G_SPHSRC | G_FRICTION;
 constexpr int FL_ALL = G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N | G_WALLMODE | G_SOLVER1 |
                        G_SPHSRC | G_FRICTION;
 
-#ifndef CLF_STEP_WAVES_PER_EU
-#define CLF_STEP_WAVES_PER_EU 2
-#endif
-
 template <class P, int ORDER, int FL>
 __global__ void __launch_bounds__(WAVE * WAVES_PER_BLOCK)
-__attribute__((amdgpu_waves_per_eu(CLF_STEP_WAVES_PER_EU)))
+__attribute__((amdgpu_waves_per_eu(2)))
 step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, int ntiles,
             StepState* st, int parity, int do_max) {
   typedef typename P::R R;
   typedef typename P::A A;
   typedef typename P::C C;
+  // Each interface is evaluated once and handed to the node on its other
+  // side, except in the y pipeline of the FP64 friction variants: there the
+  // carried interface values would raise register use past the three
+  // resident waves per SIMD, so each node evaluates both of its interfaces.
+  constexpr bool kShY = !(std::is_same<P, P64>::value && (FL & G_FRICTION) != 0);
   const int lane = threadIdx.x & (WAVE - 1);
   // the wave index is uniform across the wavefront: say so, so that the
   // tile, the row counter and the row metrics live in scalar registers
@@ -704,9 +809,10 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
     R xiL = 1, xiR = 1, xiS = 1;
     if (col_in) {
       xiL = gload((const R*)g.xib + xc);
-      xiR = gload((const R*)g.xib + xc + 1);
       xiS = gload((const R*)g.xisb + xc);
     }
+    // the lane left of the grid evaluates the edge interface of column 0
+    if (xc >= -1 && xc < nx) xiR = gload((const R*)g.xib + xc + 1);
     // Loads use clamped, always in-bounds indices; nodes outside the grid
     // only lose their existence flag (no divergent branches, no zero fill).
     const int xcl = xc < 0 ? 0 : (xc >= nx ? nx - 1 : xc);
@@ -788,7 +894,7 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
           ay.t = a.w;
           C oy;
           typename P::B ob;
-          ypipe_push<P, K>(yp, ay, r, cx, oy, ob);
+          ypipe_push<P, K, kShY>(yp, ay, r, tl.y0, cx, oy, ob);
           const int ro = r - HALO;
           if (ro >= tl.y0 && ro < ny) {
             A ax;
@@ -811,7 +917,7 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
           ay.t = a.w;
           C oy;
           typename P::B ob;
-          ypipe_push<P, K>(yp, ay, r, cx, oy, ob);
+          ypipe_push<P, K, kShY>(yp, ay, r, tl.y0, cx, oy, ob);
           const int ro = r - HALO;
           if (ro >= tl.y0) {
             C o;
