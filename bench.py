@@ -59,10 +59,10 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1410_0753_amd", "csrc", "clf_kernels.hip"
 # source they were taken on and by workload; they apply only to a launch of
 # the same workgroup count (segment length).
 TRAFFIC = {
-    "cb1ba42a641b934b97d94eb0e1a28b4cb6947024c157d0db15f76bcf65200a50": {
-        "c2/fp64": {"workgroups": 760, "read_bytes": 271400000, "write_bytes": 110400000},
-        "c2/fp32": {"workgroups": 1192, "read_bytes": 154100000, "write_bytes": 52000000},
-        "c5/fp32": {"workgroups": 5072, "read_bytes": 1387400000, "write_bytes": 599500000},
+    "e6a743dace595fcdb61386e3dcb39dac50fd474c37b516b13480241f04c94e58": {
+        "c2/fp64": {"workgroups": 760, "read_bytes": 271600000, "write_bytes": 110800000},
+        "c2/fp32": {"workgroups": 1000, "read_bytes": 146100000, "write_bytes": 52600000},
+        "c5/fp32": {"workgroups": 3072, "read_bytes": 1300600000, "write_bytes": 599400000},
     },
 }
 
