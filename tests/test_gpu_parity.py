@@ -81,6 +81,39 @@ def test_single_sweep_parity(clf, oracle_mod, axis):
     _cmp_state(g, o, bitwise=True, what="sweep %d" % axis)
 
 
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_edge_interfaces(clf, oracle_mod, axis, prec):
+    # A flow normal to every edge of a wet spherical basin with uneven
+    # spacing: the wall interface of the first row or column is evaluated
+    # from outside the grid (by the lane or pipeline row before it), so its
+    # inverse spacing must be that of the edge and not a default.
+    rng = np.random.default_rng(21)
+    nx, ny = 131, 77
+    x = 140.0 + np.cumsum(np.r_[0.0, 0.01 + 0.02 * rng.random(nx - 1)])
+    y = 20.0 + np.cumsum(np.r_[0.0, 0.01 + 0.02 * rng.random(ny - 1)])
+    d = synth.f32(1000.0 + 500.0 * rng.random((ny, nx)))
+    eta = synth.f32(0.3 * rng.standard_normal((ny, nx)))
+    u = synth.f32(np.where(np.arange(nx)[None, :] < nx // 2, -0.5, 0.5) * np.ones((ny, 1)))
+    v = synth.f32(np.where(np.arange(ny)[:, None] < ny // 2, -0.4, 0.4) * np.ones((1, nx)))
+    dt = 2.0
+    p = clf.FP64 if prec == "fp64" else clf.FP32
+    g = clf.Solver(x, y, d, dt, coord=synth.SPHERICAL, precision=p, ssl_alpha=0.0)
+    o = oracle_mod.Oracle(x, y, d, dt, coord=synth.SPHERICAL, ssl_alpha=0.0)
+    for obj in (g, o):
+        obj.set_initial(eta, u, v)
+        for _ in range(3):
+            obj.sweep(axis)
+    if prec == "fp64":
+        _cmp_state(g, o, bitwise=True, what="edge interfaces, sweep %d" % axis)
+    else:
+        e_g, u_g, v_g, _ = (t.cpu().numpy() for t in g.state())
+        e_o, u_o, v_o, _ = o.state()
+        for name, a, b in (("eta", e_g, e_o), ("u", u_g, u_o), ("v", v_g, v_o)):
+            err = np.abs(a - b).max() / np.abs(b).max()
+            assert err < 1e-5, "%s rel err %.2e" % (name, err)
+
+
 def test_raw_state_bitwise(clf, oracle_mod):
     case = synth.random_small(6, 100, 64, land=True)
     g, o = _pair(clf, case, oracle_mod)
