@@ -87,8 +87,10 @@ typedef struct clf_ctx clf_ctx;
  * x[nx], y[ny] are host arrays, strictly increasing: metres (Cartesian) or
  * decimal degrees (spherical lon/lat).  A 2-D grid needs nx, ny >= 3; a 1-D
  * grid has nx == 1 or ny == 1 and at least 3 nodes along the other axis.
- * nx * ny must be below 2^32 (the step kernel addresses a grid with 32-bit
- * element offsets); larger grids are rejected with CLF_EINVAL. */
+ * Each field array must fit in 4 GiB: nx * ny * 8 (FP64) or nx * ny * 4
+ * (FP32) must not exceed 2^32 bytes, since the step kernel reaches a node by
+ * a 32-bit byte offset from the array's base.  Larger grids are rejected
+ * with CLF_EINVAL. */
 typedef struct clf_grid {
   int32_t nx, ny;
   int32_t coord;

@@ -94,6 +94,18 @@ template <class T>
 __device__ __forceinline__ void gstore(T* p, T v) {
   *(__attribute__((address_space(1))) T*)p = v;
 }
+// An array element through a 32-bit byte offset from the array's base: the
+// access takes the uniform base in scalar registers and the offset in one
+// vector register, shared by all fields of a node (each field array is at
+// most 4 GiB; the runtime rejects larger grids).
+template <class T>
+__device__ __forceinline__ T gload_at(const T* base, unsigned boff) {
+  return *(const __attribute__((address_space(1))) T*)((const char*)base + boff);
+}
+template <class T>
+__device__ __forceinline__ void gstore_at(T* base, unsigned boff, T v) {
+  *(__attribute__((address_space(1))) T*)((char*)base + boff) = v;
+}
 
 // ---------------------------------------------------------------------------
 // FP64 node stages (literal form).
@@ -745,9 +757,17 @@ constexpr int FL_FRIC = G_SPHSRC | G_FRICTION;
 constexpr int FL_ALL = G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N | G_WALLMODE | G_SOLVER1 |
                        G_SPHSRC | G_FRICTION;
 
+// Lower bound on resident waves per SIMD handed to the register allocator.
+// The common FP64 kernel sits one register above the three-wave limit of
+// 168 VGPRs without it; with it one value spills, outside the march loop.
+template <class P, int ORDER, int FL>
+constexpr int kStepWaves() {
+  return std::is_same<P, P64>::value && FL == FL_FAST && ORDER == ORD_XY ? 3 : 2;
+}
+
 template <class P, int ORDER, int FL>
 __global__ void __launch_bounds__(WAVE * WAVES_PER_BLOCK)
-__attribute__((amdgpu_waves_per_eu(2)))
+__attribute__((amdgpu_waves_per_eu(kStepWaves<P, ORDER, FL>())))
 step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, int ntiles,
             StepState* st, int parity, int do_max) {
   typedef typename P::R R;
@@ -818,11 +838,11 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
     const int xcl = xc < 0 ? 0 : (xc >= nx ? nx - 1 : xc);
     auto load_row = [&](int r, A& a) {
       const int rc = r < 0 ? 0 : (r >= ny ? ny - 1 : r);
-      const unsigned k = (unsigned)rc * (unsigned)nx + (unsigned)xcl;  // < 2^32 elements
-      a.H = gload(cx.H + k);
-      a.D = gload(cx.D + k);
-      a.w = gload(cx.U + k);   // x view: w = u, t = v
-      a.t = gload(cx.V + k);
+      const unsigned b = ((unsigned)rc * (unsigned)nx + (unsigned)xcl) * (unsigned)sizeof(R);
+      a.H = gload_at(cx.H, b);
+      a.D = gload_at(cx.D, b);
+      a.w = gload_at(cx.U, b);   // x view: w = u, t = v
+      a.t = gload_at(cx.V, b);
       a.f = (col_in && r >= 0 && r < ny) ? F_EX : 0;
       if (kRing) a.f |= ring_flag(cx.gflags, xc, r, nx, ny);
     };
@@ -832,25 +852,25 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
       m.e = 0; m.s2 = 0;
       if (do_max) {
         const int rc = r < 0 ? 0 : (r >= ny ? ny - 1 : r);
-        const unsigned k = (unsigned)rc * (unsigned)nx + (unsigned)xcl;  // < 2^32 elements
-        m.e = gload(cx.emax + k);
-        m.s2 = gload(cx.smax2 + k);
+        const unsigned b = ((unsigned)rc * (unsigned)nx + (unsigned)xcl) * (unsigned)sizeof(R);
+        m.e = gload_at(cx.emax, b);
+        m.s2 = gload_at(cx.smax2, b);
       }
     };
     auto store = [&](int r, const C& o, R D, const MW& m) {
       // o in x view: H, w = u, t = v
       if (!out_lane || r < 0 || r >= ny) return;
-      const unsigned k = (unsigned)r * (unsigned)nx + (unsigned)xc;
-      gstore(cx.Ho + k, o.H);
-      gstore(cx.Uo + k, o.w);
-      gstore(cx.Vo + k, o.t);
+      const unsigned b = ((unsigned)r * (unsigned)nx + (unsigned)xc) * (unsigned)sizeof(R);
+      gstore_at(cx.Ho, b, o.H);
+      gstore_at(cx.Uo, b, o.w);
+      gstore_at(cx.Vo, b, o.t);
       // one test: a NaN or an infinity in any term makes the sum non-finite
       if (!isfinite((o.H + o.w) + o.t)) bad = 1;
       if (do_max && P::wet_out(o, D, cx.par)) {
         R e = P::eta_out(o, D);
-        if (e > m.e) gstore(cx.emax + k, e);
+        if (e > m.e) gstore_at(cx.emax, b, e);
         R s2 = o.w * o.w + o.t * o.t;
-        if (s2 > m.s2) gstore(cx.smax2 + k, s2);
+        if (s2 > m.s2) gstore_at(cx.smax2, b, s2);
       }
     };
 

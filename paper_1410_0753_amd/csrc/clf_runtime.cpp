@@ -571,8 +571,6 @@ static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c) {
     return fail(c, CLF_EINVAL, "a 1-D grid needs at least 3 nodes");
   if (!oned && (g->nx < 3 || g->ny < 3))
     return fail(c, CLF_EINVAL, "a 2-D grid needs at least 3 nodes per direction");
-  if ((long long)g->nx * g->ny >= (1LL << 32))
-    return fail(c, CLF_EINVAL, "nx * ny must be below 2^32 (32-bit element offsets)");
   if (g->coord != CLF_CARTESIAN && g->coord != CLF_SPHERICAL)
     return fail(c, CLF_EINVAL, "bad coordinate system");
   if (!g->x || !g->y) return fail(c, CLF_EINVAL, "null coordinates");
@@ -587,6 +585,11 @@ static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c) {
     return fail(c, CLF_EINVAL, "bad precision");
   if (p->precision == CLF_FP32 && !kHaveFp32Kernels)
     return fail(c, CLF_EINVAL, "FP32 kernels are not built into this library");
+  // the step kernel reaches a node of each field array by a 32-bit byte offset
+  const long long es = p->precision == CLF_FP64 ? 8 : 4;
+  if ((long long)g->nx * g->ny * es > (1LL << 32))
+    return fail(c, CLF_EINVAL,
+                "grid too large: each field array must fit in 4 GiB (nx * ny * %lld bytes)", es);
   if (!(p->h_min > 0.0)) return fail(c, CLF_EINVAL, "h_min must be > 0");
   if (p->manning_n2 < 0.0) return fail(c, CLF_EINVAL, "manning_n2 must be >= 0");
   if (p->solver != 1 && p->solver != 2) return fail(c, CLF_EINVAL, "solver must be 1 or 2");

@@ -51,20 +51,24 @@ def test_default_params_and_workspace_size(lib):
 
 
 def test_grid_size_limits(lib):
-    # the step kernel uses 32-bit element offsets: nx * ny must stay below 2^32
+    # the step kernel reaches a node by a 32-bit byte offset from the base of
+    # its field array: nx * ny * element size must not exceed 2^32 bytes
     from paper_1410_0753_amd import clf
     import numpy as np
-    p = clf.Params()
-    lib.clf_default_params(ctypes.byref(p))
     x = np.arange(65536.0)
     px = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     n = ctypes.c_size_t(0)
     lib.clf_workspace_bytes.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
-    big = clf.Grid(65536, 65536, 0, px, px)
-    assert lib.clf_workspace_bytes(ctypes.byref(big), ctypes.byref(p), ctypes.byref(n)) == -1
-    ok = clf.Grid(65536, 65535, 0, px, px)
-    assert lib.clf_workspace_bytes(ctypes.byref(ok), ctypes.byref(p), ctypes.byref(n)) == 0
-    assert n.value >= 9 * 8 * 65536 * 65535
+    for prec, es, nx in ((clf.FP64, 8, 32768), (clf.FP32, 4, 65536)):
+        p = clf.Params()
+        lib.clf_default_params(ctypes.byref(p))
+        p.precision = prec
+        ny = (1 << 32) // (es * nx)
+        ok = clf.Grid(nx, ny, 0, px, px)
+        assert lib.clf_workspace_bytes(ctypes.byref(ok), ctypes.byref(p), ctypes.byref(n)) == 0
+        assert n.value >= 9 * es * nx * ny
+        big = clf.Grid(nx, ny + 1, 0, px, px)
+        assert lib.clf_workspace_bytes(ctypes.byref(big), ctypes.byref(p), ctypes.byref(n)) == -1
 
 
 def _ws(lib, grid, params):
