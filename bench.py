@@ -59,10 +59,10 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1410_0753_amd", "csrc", "clf_kernels.hip"
 # source they were taken on and by workload; they apply only to a launch of
 # the same workgroup count (segment length).
 TRAFFIC = {
-    "e6a743dace595fcdb61386e3dcb39dac50fd474c37b516b13480241f04c94e58": {
-        "c2/fp64": {"workgroups": 760, "read_bytes": 271600000, "write_bytes": 110800000},
-        "c2/fp32": {"workgroups": 1000, "read_bytes": 146100000, "write_bytes": 52600000},
-        "c5/fp32": {"workgroups": 3072, "read_bytes": 1300600000, "write_bytes": 599400000},
+    "0c04ffb533854fedaffc9ac2d850908b473b8a4e168a5f12814c64ef3ce9dd6a": {
+        "c2/fp64": {"workgroups": 760, "read_bytes": 272200000, "write_bytes": 111500000},
+        "c2/fp32": {"workgroups": 1000, "read_bytes": 146100000, "write_bytes": 52700000},
+        "c5/fp32": {"workgroups": 3072, "read_bytes": 1301000000, "write_bytes": 600700000},
     },
 }
 
