@@ -389,8 +389,9 @@ def main():
                     help="also run one 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(every run here uses exactly one MI355X)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(the y-band sharding design is described but not built); use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     if args.profile:
         args.steps, args.warmup = min(args.steps, 20), min(args.warmup, 3)
