@@ -151,6 +151,24 @@ def test_friction_parity(clf, oracle_mod, coord):
     _cmp_state(g, o, tol=TOL, what="friction")
 
 
+@pytest.mark.parametrize("opts", [
+    dict(sweep_order=1),
+    dict(solver=1),
+    dict(itopo=0, dwall=5.0),
+    dict(sweep_order=1, solver=1, itopo=0, dwall=5.0),
+], ids=["alternate", "solver1", "wallmode", "all"])
+@pytest.mark.parametrize("coord", [synth.CARTESIAN, synth.SPHERICAL], ids=["cartesian", "spherical"])
+def test_friction_with_options(clf, oracle_mod, opts, coord):
+    # friction selects its own kernel variants (the y update per node in
+    # FP64, and the general variant with solver1 or wall mode)
+    case = synth.random_small(16, 85, 64, land=True, coord=coord)
+    g, o = _pair(clf, case, oracle_mod, manning_n2=0.0009, **opts)
+    for obj in (g, o):
+        obj.set_initial(case.eta0 * 2.0, case.u0, case.v0)
+        obj.step(13)
+    _cmp_state(g, o, tol=TOL, what="friction %s" % opts)
+
+
 @pytest.mark.parametrize("shape", [(1, 150), (150, 1)], ids=["1d-x", "1d-y"])
 def test_one_d_parity(clf, oracle_mod, shape):
     ny, nx = shape
