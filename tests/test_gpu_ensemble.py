@@ -54,6 +54,28 @@ def test_members_equal_single_runs(clf, prec, opts):
         assert ens.query(clf.Q_GRAPH_REPLAYS) == 3
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_members_equal_single_runs_with_friction(clf, prec):
+    # the friction variants over the combined tile list, spherical members too
+    p = clf.FP64 if prec == "fp64" else clf.FP32
+    cases = [synth.random_small(50 + k, 70 + 13 * k, 40 + 9 * k, land=True,
+                                coord=synth.SPHERICAL if k % 2 else synth.CARTESIAN)
+             for k in range(4)]
+    ref = []
+    for c in cases:
+        s = clf.Solver.from_case(c, precision=p, graph_steps=0, manning_n2=0.0009)
+        s.set_initial(c.eta0, c.u0, c.v0)
+        s.step(9)
+        ref.append([t.cpu().numpy() for t in s.state()])
+    ens = clf.Ensemble(cases, precision=p, graph_steps=0, manning_n2=0.0009)
+    for i, c in enumerate(cases):
+        ens.set_initial(i, c.eta0, c.u0, c.v0)
+    ens.step(9)
+    for i in range(len(cases)):
+        for a, b in zip((t.cpu().numpy() for t in ens.state(i)), ref[i]):
+            assert np.array_equal(a, b), "member %d differs" % i
+
+
 def test_graph_replays_match_eager_each_time(clf):
     cases = members()[:4]
     g = clf.Ensemble(cases, precision=clf.FP32, graph_steps=2)
