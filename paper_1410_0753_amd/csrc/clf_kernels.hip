@@ -702,7 +702,8 @@ struct YPipe {
 
 // Push row r (y view: w = v, t = u) in phase K; returns the final state of
 // row r-3 in `out` and its post-(b) view (flags, depth, flood source) in `ob`.
-// y0 is the first row the segment writes.
+// y0 is the first row the segment writes.  SH: interfaces are evaluated once
+// and carried to the next push (else each node evaluates both of its own).
 template <class P, int K, bool SH>
 __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_in, int r,
                                            int y0, const Ctx<P>& cx, typename P::C& out,
