@@ -59,7 +59,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1410_0753_amd", "csrc", "clf_kernels.hip"
 # source they were taken on and by workload; they apply only to a launch of
 # the same workgroup count (segment length).
 TRAFFIC = {
-    "8cfc936a0bea82d1262b42dc75e0e6e79e0f79a98ce129f506211230a4a11507": {
+    "ad1dc39e5f56ee1dd608f797a7491d17675be488d79a4a35b0458b0360b46465": {
         "c2/fp64": {"workgroups": 760, "read_bytes": 272200000, "write_bytes": 111500000},
         "c2/fp32": {"workgroups": 1000, "read_bytes": 146100000, "write_bytes": 52700000},
         "c5/fp32": {"workgroups": 3072, "read_bytes": 1301000000, "write_bytes": 600700000},

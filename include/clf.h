@@ -80,6 +80,7 @@ extern "C" {
 #define CLF_Q_SEGMENT 8        /* rows per wavefront tile (autotuned) */
 #define CLF_Q_BLOCKS 9         /* workgroups per step kernel launch */
 #define CLF_Q_GRAPH_REPLAYS 10 /* hipGraph replays issued so far */
+#define CLF_Q_WIDE 11          /* 1 if the step kernel runs its 64-bit-address variant */
 
 typedef struct clf_ctx clf_ctx;
 
@@ -87,10 +88,12 @@ typedef struct clf_ctx clf_ctx;
  * x[nx], y[ny] are host arrays, strictly increasing: metres (Cartesian) or
  * decimal degrees (spherical lon/lat).  A 2-D grid needs nx, ny >= 3; a 1-D
  * grid has nx == 1 or ny == 1 and at least 3 nodes along the other axis.
- * Each field array must fit in 4 GiB: nx * ny * 8 (FP64) or nx * ny * 4
- * (FP32) must not exceed 2^32 bytes, since the step kernel reaches a node by
- * a 32-bit byte offset from the array's base.  Larger grids are rejected
- * with CLF_EINVAL. */
+ * nx * ny must be below 2^32; larger grids are rejected with CLF_EINVAL.
+ * Grids whose field arrays exceed 4 GiB (nx * ny * 8 in FP64, * 4 in FP32)
+ * run a variant of the step kernel with 64-bit addresses, which carries every
+ * option and is somewhat slower (CLF_Q_WIDE reports it).  The environment
+ * variable CLF_WIDE_OFFSETS=1, read at init, selects that variant for any
+ * grid. */
 typedef struct clf_grid {
   int32_t nx, ny;
   int32_t coord;

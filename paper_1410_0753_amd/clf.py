@@ -24,7 +24,7 @@ FP64, FP32 = 0, 1
 ORDER_XY, ORDER_ALTERNATE = 0, 1
 WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
 (Q_MAX_CFL, Q_SSL_PASSES, Q_STEP, Q_MIN_F, Q_WORKSPACE, Q_GAUGE_RECORDS, Q_TILES, Q_SEGMENT,
- Q_BLOCKS, Q_GRAPH_REPLAYS) = range(1, 11)
+ Q_BLOCKS, Q_GRAPH_REPLAYS, Q_WIDE) = range(1, 12)
 
 # Every symbol include/clf.h declares.
 EXPORTS = ["clf_default_params", "clf_workspace_bytes", "clf_init", "clf_set_initial",

@@ -25,6 +25,7 @@ enum : int {
   G_SOLVER1 = 32,
   G_SPHSRC = 64,    // tan(lat) continuity source in the y-sweep
   G_FRICTION = 128,
+  G_WIDE = 256,     // field arrays above 4 GiB: 64-bit addresses in the step kernel
 };
 
 // kernel orders

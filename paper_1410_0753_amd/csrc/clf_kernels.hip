@@ -96,8 +96,8 @@ __device__ __forceinline__ void gstore(T* p, T v) {
 }
 // An array element through a 32-bit byte offset from the array's base: the
 // access takes the uniform base in scalar registers and the offset in one
-// vector register, shared by all fields of a node (each field array is at
-// most 4 GiB; the runtime rejects larger grids).
+// vector register, shared by all fields of a node (field arrays up to 4 GiB;
+// larger ones take the 64-bit variant of the step kernel).
 template <class T>
 __device__ __forceinline__ T gload_at(const T* base, unsigned boff) {
   return *(const __attribute__((address_space(1))) T*)((const char*)base + boff);
@@ -757,6 +757,8 @@ constexpr int FL_FAST = G_SPHSRC;
 constexpr int FL_FRIC = G_SPHSRC | G_FRICTION;
 constexpr int FL_ALL = G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N | G_WALLMODE | G_SOLVER1 |
                        G_SPHSRC | G_FRICTION;
+// grids whose field arrays exceed 4 GiB: every option, 64-bit addresses
+constexpr int FL_WIDE = FL_ALL | G_WIDE;
 
 // Lower bound on resident waves per SIMD handed to the register allocator.
 // The common FP64 kernel sits one register above the three-wave limit of
@@ -837,13 +839,24 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
     // Loads use clamped, always in-bounds indices; nodes outside the grid
     // only lose their existence flag (no divergent branches, no zero fill).
     const int xcl = xc < 0 ? 0 : (xc >= nx ? nx - 1 : xc);
+    // node offsets: bytes in 32 bits, or elements (below 2^32) with 64-bit
+    // address arithmetic for field arrays above 4 GiB
+    constexpr bool kWide = (FL & G_WIDE) != 0;
+    auto node = [&](int r, int x) -> unsigned {
+      const unsigned k = (unsigned)r * (unsigned)nx + (unsigned)x;
+      return kWide ? k : k * (unsigned)sizeof(R);
+    };
+    auto ld = [&](const R* base, unsigned o) { return kWide ? gload(base + o) : gload_at(base, o); };
+    auto put = [&](R* base, unsigned o, R v) {
+      if (kWide) gstore(base + o, v); else gstore_at(base, o, v);
+    };
     auto load_row = [&](int r, A& a) {
       const int rc = r < 0 ? 0 : (r >= ny ? ny - 1 : r);
-      const unsigned b = ((unsigned)rc * (unsigned)nx + (unsigned)xcl) * (unsigned)sizeof(R);
-      a.H = gload_at(cx.H, b);
-      a.D = gload_at(cx.D, b);
-      a.w = gload_at(cx.U, b);   // x view: w = u, t = v
-      a.t = gload_at(cx.V, b);
+      const unsigned b = node(rc, xcl);
+      a.H = ld(cx.H, b);
+      a.D = ld(cx.D, b);
+      a.w = ld(cx.U, b);   // x view: w = u, t = v
+      a.t = ld(cx.V, b);
       a.f = (col_in && r >= 0 && r < ny) ? F_EX : 0;
       if (kRing) a.f |= ring_flag(cx.gflags, xc, r, nx, ny);
     };
@@ -853,25 +866,25 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
       m.e = 0; m.s2 = 0;
       if (do_max) {
         const int rc = r < 0 ? 0 : (r >= ny ? ny - 1 : r);
-        const unsigned b = ((unsigned)rc * (unsigned)nx + (unsigned)xcl) * (unsigned)sizeof(R);
-        m.e = gload_at(cx.emax, b);
-        m.s2 = gload_at(cx.smax2, b);
+        const unsigned b = node(rc, xcl);
+        m.e = ld(cx.emax, b);
+        m.s2 = ld(cx.smax2, b);
       }
     };
     auto store = [&](int r, const C& o, R D, const MW& m) {
       // o in x view: H, w = u, t = v
       if (!out_lane || r < 0 || r >= ny) return;
-      const unsigned b = ((unsigned)r * (unsigned)nx + (unsigned)xc) * (unsigned)sizeof(R);
-      gstore_at(cx.Ho, b, o.H);
-      gstore_at(cx.Uo, b, o.w);
-      gstore_at(cx.Vo, b, o.t);
+      const unsigned b = node(r, xc);
+      put(cx.Ho, b, o.H);
+      put(cx.Uo, b, o.w);
+      put(cx.Vo, b, o.t);
       // one test: a NaN or an infinity in any term makes the sum non-finite
       if (!isfinite((o.H + o.w) + o.t)) bad = 1;
       if (do_max && P::wet_out(o, D, cx.par)) {
         R e = P::eta_out(o, D);
-        if (e > m.e) gstore_at(cx.emax, b, e);
+        if (e > m.e) put(cx.emax, b, e);
         R s2 = o.w * o.w + o.t * o.t;
-        if (s2 > m.s2) gstore_at(cx.smax2, b, s2);
+        if (s2 > m.s2) put(cx.smax2, b, s2);
       }
     };
 
@@ -1233,7 +1246,12 @@ hipError_t launch_step(int fp32, int order, int gflags, const GridDesc* grids, c
   dim3 grid(nblocks), block(WAVE * WAVES_PER_BLOCK);
   const bool fast = (gflags & ~FL_FAST) == 0;
   const bool fric = (gflags & ~FL_FRIC) == 0;
-  if (fp32) {
+  if (gflags & G_WIDE) {
+    if (fp32)
+      launch_order<P32, FL_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+    else
+      launch_order<P64, FL_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+  } else if (fp32) {
     if (fast)
       launch_order<P32, FL_FAST>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
     else if (fric)
@@ -1274,6 +1292,8 @@ hipError_t step_blocks_per_cu(int fp32, int order, int gflags, int* n) {
   *n = 0;
   const bool fast = (gflags & ~FL_FAST) == 0;
   const bool fric = (gflags & ~FL_FRIC) == 0;
+  if (gflags & G_WIDE)
+    return fp32 ? occupancy_of<P32, FL_WIDE>(order, n) : occupancy_of<P64, FL_WIDE>(order, n);
   if (fp32)
     return fast ? occupancy_of<P32, FL_FAST>(order, n)
                 : (fric ? occupancy_of<P32, FL_FRIC>(order, n) : occupancy_of<P32, FL_ALL>(order, n));

@@ -563,6 +563,17 @@ void clf_default_params(clf_params* p) {
   p->persistent_blocks = 0;
 }
 
+// Field arrays above 4 GiB take the step kernel's 64-bit-address variant
+// (the common variants reach a node by a 32-bit byte offset).  Setting the
+// environment variable CLF_WIDE_OFFSETS=1 selects it for every grid, so that
+// it can be checked on small ones.
+static bool wide_offsets(int nx, int ny, int fp32) {
+  const long long es = fp32 ? 4 : 8;
+  if ((long long)nx * ny * es > (1LL << 32)) return true;
+  const char* e = std::getenv("CLF_WIDE_OFFSETS");
+  return e && e[0] == '1';
+}
+
 static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c) {
   if (!g || !p) return fail(c, CLF_EINVAL, "null grid or params");
   if (g->nx < 1 || g->ny < 1) return fail(c, CLF_EINVAL, "nx, ny must be >= 1");
@@ -585,11 +596,9 @@ static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c) {
     return fail(c, CLF_EINVAL, "bad precision");
   if (p->precision == CLF_FP32 && !kHaveFp32Kernels)
     return fail(c, CLF_EINVAL, "FP32 kernels are not built into this library");
-  // the step kernel reaches a node of each field array by a 32-bit byte offset
-  const long long es = p->precision == CLF_FP64 ? 8 : 4;
-  if ((long long)g->nx * g->ny * es > (1LL << 32))
-    return fail(c, CLF_EINVAL,
-                "grid too large: each field array must fit in 4 GiB (nx * ny * %lld bytes)", es);
+  // node offsets in the step kernel are 32-bit element counts
+  if ((long long)g->nx * g->ny >= (1LL << 32))
+    return fail(c, CLF_EINVAL, "grid too large: nx * ny must be below 2^32");
   if (!(p->h_min > 0.0)) return fail(c, CLF_EINVAL, "h_min must be > 0");
   if (p->manning_n2 < 0.0) return fail(c, CLF_EINVAL, "manning_n2 must be >= 0");
   if (p->solver != 1 && p->solver != 2) return fail(c, CLF_EINVAL, "solver must be 1 or 2");
@@ -721,6 +730,7 @@ static int ctx_create(clf_ctx** out, const clf_grid* g, const double* depth, dou
   if (p->itopo == 0) flags |= G_WALLMODE;
   if (p->solver == 1) flags |= G_SOLVER1;
   if (p->manning_n2 > 0.0) flags |= G_FRICTION;
+  if (wide_offsets(c->nx, c->ny, c->fp32)) flags |= G_WIDE;
   gd.flags = flags;
   gd.maxout = p->maxout;
   gd.H[0] = b + L.f[0]; gd.H[1] = b + L.f[1];
@@ -1207,6 +1217,7 @@ int clf_query(clf_ctx* c, int what, double* value) {
     case CLF_Q_SEGMENT: *value = c->seg; break;
     case CLF_Q_BLOCKS: *value = eff_blocks(c->nblocks, c->p.persistent_blocks); break;
     case CLF_Q_GRAPH_REPLAYS: *value = (double)c->graph_replays; break;
+    case CLF_Q_WIDE: *value = (c->gd.flags & G_WIDE) ? 1.0 : 0.0; break;
     default: return fail(c, CLF_EINVAL, "unknown query %d", what);
   }
   return CLF_OK;
@@ -1762,6 +1773,7 @@ int clf_ensemble_query(clf_ens* e, int what, double* value) {
     case CLF_Q_SEGMENT: *value = e->seg; break;
     case CLF_Q_BLOCKS: *value = eff_blocks(e->nblocks, e->p.persistent_blocks); break;
     case CLF_Q_GRAPH_REPLAYS: *value = (double)e->graph_replays; break;
+    case CLF_Q_WIDE: *value = (e->gflags & G_WIDE) ? 1.0 : 0.0; break;
     case CLF_Q_WORKSPACE: {
       double tot = 0;
       for (auto* c : e->m) tot += (double)c->L.total;

@@ -51,23 +51,23 @@ def test_default_params_and_workspace_size(lib):
 
 
 def test_grid_size_limits(lib):
-    # the step kernel reaches a node by a 32-bit byte offset from the base of
-    # its field array: nx * ny * element size must not exceed 2^32 bytes
+    # node offsets in the step kernel are 32-bit element counts: nx * ny must
+    # stay below 2^32 (field arrays above 4 GiB run the 64-bit-address
+    # variant, which is checked on small grids in the GPU tests)
     from paper_1410_0753_amd import clf
     import numpy as np
     x = np.arange(65536.0)
     px = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     n = ctypes.c_size_t(0)
     lib.clf_workspace_bytes.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
-    for prec, es, nx in ((clf.FP64, 8, 32768), (clf.FP32, 4, 65536)):
+    for prec, es in ((clf.FP64, 8), (clf.FP32, 4)):
         p = clf.Params()
         lib.clf_default_params(ctypes.byref(p))
         p.precision = prec
-        ny = (1 << 32) // (es * nx)
-        ok = clf.Grid(nx, ny, 0, px, px)
+        ok = clf.Grid(65536, 65535, 0, px, px)
         assert lib.clf_workspace_bytes(ctypes.byref(ok), ctypes.byref(p), ctypes.byref(n)) == 0
-        assert n.value >= 9 * es * nx * ny
-        big = clf.Grid(nx, ny + 1, 0, px, px)
+        assert n.value >= 9 * es * 65536 * 65535
+        big = clf.Grid(65536, 65536, 0, px, px)
         assert lib.clf_workspace_bytes(ctypes.byref(big), ctypes.byref(p), ctypes.byref(n)) == -1
 
 
