@@ -125,6 +125,30 @@ def test_wide_fp32_and_ensemble(clf, oracle_mod, wide):
             assert np.array_equal(a, b), "member %d" % i
 
 
+def test_wide_adjoint_equals_narrow(clf):
+    # the adjoint's recomputed sweeps run the same arithmetic either way
+    c = synth.random_small(61, 70, 52, land=True, amp=0.3)
+    gx = np.array([5, 30, 60, 44]); gy = np.array([10, 25, 40, 7])
+    nsteps = 30
+    obs = 0.05 * np.random.default_rng(4).standard_normal((nsteps // 2 + 1, len(gx)))
+    grads = []
+    for flag in ("0", "1"):
+        os.environ["CLF_WIDE_OFFSETS"] = flag
+        try:
+            s = clf.Solver.from_case(c, gout=2)
+            assert s.query(clf.Q_WIDE) == int(flag)
+            s.set_gauges(gx, gy)
+            s.set_initial(c.eta0)
+            s.adjoint_forward(nsteps, 0)
+            rec, _ = s.read_gauges()
+            adj = np.zeros_like(rec)
+            adj[:, :, 0] = rec[:, :, 0] - obs
+            grads.append(s.adjoint_backward(adj)[0].cpu().numpy())
+        finally:
+            del os.environ["CLF_WIDE_OFFSETS"]
+    assert np.array_equal(grads[0], grads[1])
+
+
 def test_narrow_by_default(clf):
     assert "CLF_WIDE_OFFSETS" not in os.environ or os.environ["CLF_WIDE_OFFSETS"] != "1"
     case = synth.random_small(20, 40, 30, land=True)
