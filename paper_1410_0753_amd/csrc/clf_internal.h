@@ -61,8 +61,9 @@ struct StepState {
 // Work tile of one wavefront: grid index, first output column, first
 // output row, number of output rows.
 struct Tile {
-  int grid, x0, y0, rows;
+  int grid, x0, y0, rows;   // grid | kTileReverse: the segment marches rows downward
 };
+constexpr int kTileReverse = 1 << 30;
 
 // Per-point sampling tables.
 struct SampleDesc {

@@ -700,55 +700,74 @@ struct YPipe {
   }
 };
 
-// Push row r (y view: w = v, t = u) in phase K; returns the final state of
-// row r-3 in `out` and its post-(b) view (flags, depth, flood source) in `ob`.
-// y0 is the first row the segment writes.  SH: interfaces are evaluated once
-// and carried to the next push (else each node evaluates both of its own).
-template <class P, int K, bool SH>
+// Push row r (y view: w = v, t = u) in phase K of a march in direction D
+// (+1: rows in increasing index, -1: decreasing); returns the final state of
+// row r - 3D in `out` and its post-(b) view (flags, depth, flood source) in
+// `ob`.  The segment writes rows y0..ylast.  SH: interfaces are evaluated
+// once and carried to the next push (else each node evaluates both of its
+// own).  "Lower" and "upper" below are row indices; a node's stages see its
+// lower neighbour as left and its upper neighbour as right in either
+// direction, so every node computes the same bits.
+template <class P, int K, bool SH, int D>
 __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_in, int r,
-                                           int y0, const Ctx<P>& cx, typename P::C& out,
-                                           typename P::B& ob) {
+                                           int y0, int ylast, const Ctx<P>& cx,
+                                           typename P::C& out, typename P::B& ob) {
   typedef typename P::R R;
   constexpr int K1 = (K + 1) % 3, K2 = (K + 2) % 3;
+  // window slots by row: a[K] = r, a[K2] = r - D, a[K1] = r - 2D (likewise b
+  // one row behind a, c two rows behind)
+  constexpr int AL = D > 0 ? K1 : K, AU = D > 0 ? K : K1;
   y.a[K] = a_in;
   P::stage_a(y.a[K], cx.par);
-  // (b) on row r-1 (centre a[K2]); the flooding logic runs only when some
+  // (b) on row r - D (centre a[K2]); the flooding logic runs only when some
   // lane of the wavefront has a dry node next to a wet one
-  if (__ballot(P::flood_candidate(y.a[K2].f, y.a[K1].f, y.a[K].f)) != 0)
-    y.b[K] = P::stage_b(y.a[K1], y.a[K2], y.a[K], cx.par);
+  if (__ballot(P::flood_candidate(y.a[K2].f, y.a[AL].f, y.a[AU].f)) != 0)
+    y.b[K] = P::stage_b(y.a[AL], y.a[K2], y.a[AU], cx.par);
   else
     y.b[K] = P::stage_b_copy(y.a[K2]);
   P::set_c(y.b[K]);
-  // (c)+(d) on row r-2
-  const int rc = r - 2;
+  // (c)+(d) on row rc = r - 2D (centre b[K2]; b[K] = row r - D, b[K1] = row r - 3D)
+  constexpr int BL = D > 0 ? K1 : K, BU = D > 0 ? K : K1;
+  const int rc = r - 2 * D;
   R iL = 1, iR = 1, iS = 1, tr = 0;
   if (rc >= 0 && rc < cx.ny) {
-    iL = cload(cx.yib + rc);
     iS = cload(cx.yisb + rc);
     if (cx.par.flags & G_SPHSRC) tr = cload(cx.tanR + rc);
   }
-  // the interface below row rc is also that above row rc + 1, so its
-  // spacing is needed from row -1 on (the edge interface of row 0)
+  // the interface between rows k and k + 1 has spacing index k + 1; the edge
+  // interfaces of rows 0 and ny - 1 are evaluated from rows -1 and ny
+  if (rc >= 0 && rc <= cx.ny) iL = cload(cx.yib + rc);
   if (rc >= -1 && rc < cx.ny) iR = cload(cx.yib + rc + 1);
   if (!SH || (cx.par.flags & G_SOLVER1)) {
-    y.c[K] = P::stage_cd(P::bx(y.b[K1]), y.b[K2], P::bx(y.b[K]), iL, iR, iS, tr, cx.par);
-  } else {
-    // the interface above row r-2 was evaluated by the previous push (as the
-    // one below row r-3); evaluate the one below and keep it for the next.
+    y.c[K] = P::stage_cd(P::bx(y.b[BL]), y.b[K2], P::bx(y.b[BU]), iL, iR, iS, tr, cx.par);
+  } else if (D > 0) {
+    // the interface above row rc was evaluated by the previous push (as the
+    // one below row rc - 1); evaluate the one below and keep it for the next.
     // Rows above y0 - 1 only feed rows above the segment, so their update is
     // skipped (a uniform branch), and of row y0 - 2 only the interface below
     // it is kept.
     if (rc >= y0 - 2) {
       const typename P::Fx FR =
-          P::interface(y.b[K2], is_real(y.b[K2].f), P::bx(y.b[K]), is_real(y.b[K].f), iR);
+          P::interface(y.b[K2], is_real(y.b[K2].f), P::bx(y.b[BU]), is_real(y.b[BU].f), iR);
       if (rc >= y0 - 1) y.c[K] = P::stage_cd_shared(y.b[K2], y.F[K2], FR, iS, tr, cx.par);
       y.F[K] = FR;
     }
+  } else {
+    // mirrored: the interface below row rc came from the previous push;
+    // evaluate the one above (rows below ylast + 1 feed nothing written)
+    if (rc <= ylast + 2) {
+      const typename P::Fx FL =
+          P::interface(y.b[BL], is_real(y.b[BL].f), P::bx(y.b[K2]), is_real(y.b[K2].f), iL);
+      if (rc <= ylast + 1) y.c[K] = P::stage_cd_shared(y.b[K2], FL, y.F[K2], iS, tr, cx.par);
+      y.F[K] = FL;
+    }
   }
-  // (e) on row r-3
+  // (e) on row r - 3D (c[K2]; c[K] = row r - 2D, c[K1] = row r - 4D)
+  constexpr int CL = D > 0 ? K1 : K, CU = D > 0 ? K : K1;
   out = y.c[K2];
   ob = y.b[K1];
-  if (__ballot(ob.src != 0) != 0) P::stage_e(out, P::cx(y.c[K1]), P::cx(y.c[K]), ob.src, ob.D);
+  if (__ballot(ob.src != 0) != 0)
+    P::stage_e(out, P::cx(y.c[CL]), P::cx(y.c[CU]), ob.src, ob.D);
 }
 
 // FL: the grid flags this instantiation honours (others are compiled out).
@@ -792,6 +811,8 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
   for (int tid = blockIdx.x * WAVES_PER_BLOCK + wave; tid < ntiles; tid += stride) {
     Tile tl = tiles[tid];
     tl.grid = __builtin_amdgcn_readfirstlane(tl.grid);
+    const bool rev = (tl.grid & kTileReverse) != 0;
+    tl.grid &= ~kTileReverse;
     tl.x0 = __builtin_amdgcn_readfirstlane(tl.x0);
     tl.y0 = __builtin_amdgcn_readfirstlane(tl.y0);
     tl.rows = __builtin_amdgcn_readfirstlane(tl.rows);
@@ -903,68 +924,82 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
         store(r, o, a.D, m);
       }
     } else {
-      YPipe<P> yp;
-      yp.reset();
-      A pf[3];
-      MW pm[3];
-      const int r_first = tl.y0 - HALO, r_end = tl.y0 + tl.rows + HALO;
-      // rows are loaded PF = P::kPrefetch march rows ahead of use (1 or 2:
-      // the three slots hold the row in use and up to two in flight)
-      constexpr int PF = P::kPrefetch;
-      load_row(r_first, pf[0]);
-      if (PF == 2) load_row(r_first + 1, pf[1]);
-      load_mw(r_first - HALO, pm[0]);
-      // one march row in phase K: consume pf[K] (row r) and pm[K] (maxwave of
-      // the output row r-3); prefetch row r+PF and the maxwave of row r-2
-      auto body = [&](auto phase, int r) {
-        constexpr int K = decltype(phase)::value;
-        A a = pf[K];
-        MW m = pm[K];
-        load_row(r + PF, pf[(K + PF) % 3]);
-        load_mw(r + 1 - HALO, pm[(K + 1) % 3]);
-        if (ORDER == ORD_YX) {
-          A ay = a;
-          ay.w = a.t;
-          ay.t = a.w;
-          C oy;
-          typename P::B ob;
-          ypipe_push<P, K, kShY>(yp, ay, r, tl.y0, cx, oy, ob);
-          const int ro = r - HALO;
-          if (ro >= tl.y0 && ro < ny) {
-            A ax;
-            ax.H = oy.H; ax.w = oy.t; ax.t = oy.w;
-            ax.f = ob.f & (F_EX | F_FIX);
-            ax.D = ob.D;
-            R f = cload(xfac + ro);
-            C o = xsweep_row<P>(ax, f * xiL, f * xiR, f * xiS, cx.par);
-            store(ro, o, ax.D, m);
+      // Alternate segment rows march in opposite directions, so that two
+      // vertically adjacent segments read the rows around their common edge
+      // at the same phase of their marches (both at the start or both at
+      // the end), when one XCD's L2 can serve the second read.
+      auto march = [&](auto dir) {
+        constexpr int D = decltype(dir)::value;
+        YPipe<P> yp;
+        yp.reset();
+        A pf[3];
+        MW pm[3];
+        const int ylast = tl.y0 + tl.rows - 1;
+        const int r_first = D > 0 ? tl.y0 - HALO : ylast + HALO;
+        const int npush = tl.rows + 2 * HALO;
+        // rows are loaded PF = P::kPrefetch march rows ahead of use (1 or 2:
+        // the three slots hold the row in use and up to two in flight)
+        constexpr int PF = P::kPrefetch;
+        load_row(r_first, pf[0]);
+        if (PF == 2) load_row(r_first + D, pf[1]);
+        load_mw(r_first - D * HALO, pm[0]);
+        // one march row in phase K: consume pf[K] (row r) and pm[K] (maxwave
+        // of the output row r - 3D); prefetch row r + PF D and the maxwave of
+        // the next output row
+        auto body = [&](auto phase, int r) {
+          constexpr int K = decltype(phase)::value;
+          A a = pf[K];
+          MW m = pm[K];
+          load_row(r + D * PF, pf[(K + PF) % 3]);
+          load_mw(r + D * (1 - HALO), pm[(K + 1) % 3]);
+          const int ro = r - D * HALO;
+          const bool writes = D > 0 ? ro >= tl.y0 : ro <= ylast;
+          if (ORDER == ORD_YX) {
+            A ay = a;
+            ay.w = a.t;
+            ay.t = a.w;
+            C oy;
+            typename P::B ob;
+            ypipe_push<P, K, kShY, D>(yp, ay, r, tl.y0, ylast, cx, oy, ob);
+            if (writes && ro < ny) {
+              A ax;
+              ax.H = oy.H; ax.w = oy.t; ax.t = oy.w;
+              ax.f = ob.f & (F_EX | F_FIX);
+              ax.D = ob.D;
+              R f = cload(xfac + ro);
+              C o = xsweep_row<P>(ax, f * xiL, f * xiR, f * xiS, cx.par);
+              store(ro, o, ax.D, m);
+            }
+          } else {
+            if (ORDER == ORD_XY && r >= 0 && r < ny) {
+              R f = cload(xfac + r);
+              C o = xsweep_row<P>(a, f * xiL, f * xiR, f * xiS, cx.par);
+              a.H = o.H; a.w = o.w; a.t = o.t;
+              a.f &= (F_EX | F_FIX);
+            }
+            A ay = a;   // y view: w = v, t = u
+            ay.w = a.t;
+            ay.t = a.w;
+            C oy;
+            typename P::B ob;
+            ypipe_push<P, K, kShY, D>(yp, ay, r, tl.y0, ylast, cx, oy, ob);
+            if (writes) {
+              C o;
+              o.H = oy.H; o.w = oy.t; o.t = oy.w;   // back to x view
+              store(ro, o, ob.D, m);
+            }
           }
-        } else {
-          if (ORDER == ORD_XY && r >= 0 && r < ny) {
-            R f = cload(xfac + r);
-            C o = xsweep_row<P>(a, f * xiL, f * xiR, f * xiS, cx.par);
-            a.H = o.H; a.w = o.w; a.t = o.t;
-            a.f &= (F_EX | F_FIX);
-          }
-          A ay = a;   // y view: w = v, t = u
-          ay.w = a.t;
-          ay.t = a.w;
-          C oy;
-          typename P::B ob;
-          ypipe_push<P, K, kShY>(yp, ay, r, tl.y0, cx, oy, ob);
-          const int ro = r - HALO;
-          if (ro >= tl.y0) {
-            C o;
-            o.H = oy.H; o.w = oy.t; o.t = oy.w;   // back to x view
-            store(ro, o, ob.D, m);
-          }
+        };
+        for (int i = 0; i < npush; i += 3) {
+          body(std::integral_constant<int, 0>(), r_first + D * i);
+          if (i + 1 < npush) body(std::integral_constant<int, 1>(), r_first + D * (i + 1));
+          if (i + 2 < npush) body(std::integral_constant<int, 2>(), r_first + D * (i + 2));
         }
       };
-      for (int r = r_first; r < r_end; r += 3) {
-        body(std::integral_constant<int, 0>(), r);
-        if (r + 1 < r_end) body(std::integral_constant<int, 1>(), r + 1);
-        if (r + 2 < r_end) body(std::integral_constant<int, 2>(), r + 2);
-      }
+      if (rev)
+        march(std::integral_constant<int, -1>());
+      else
+        march(std::integral_constant<int, 1>());
     }
   }
   if (bad) st->bad = 1;

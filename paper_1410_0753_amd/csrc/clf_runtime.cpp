@@ -287,13 +287,15 @@ hipError_t upload_any(int fp32, const std::vector<double>& v, void* dst, hipStre
 }
 
 // Natural tile order: segment rows top to bottom, strips left to right.
+// Odd segment rows march in decreasing row order, so that adjacent segment
+// rows read their shared halo rows at the same phase of their marches.
 void natural_tiles(int grid, int nx, int ny, int seg, std::vector<Tile>& t) {
   const int ns = strips_of(nx);
   const int nsegs = (ny + seg - 1) / seg;
   for (int q = 0; q < nsegs; ++q)
     for (int s = 0; s < ns; ++s) {
       Tile tl;
-      tl.grid = grid;
+      tl.grid = grid | ((q & 1) ? kTileReverse : 0);
       tl.x0 = s * STRIP;
       tl.y0 = q * seg;
       tl.rows = std::min(seg, ny - q * seg);
