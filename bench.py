@@ -59,10 +59,10 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1410_0753_amd", "csrc", "clf_kernels.hip"
 # source they were taken on and by workload; they apply only to a launch of
 # the same workgroup count (segment length).
 TRAFFIC = {
-    "ad1dc39e5f56ee1dd608f797a7491d17675be488d79a4a35b0458b0360b46465": {
-        "c2/fp64": {"workgroups": 760, "read_bytes": 272200000, "write_bytes": 111500000},
-        "c2/fp32": {"workgroups": 1000, "read_bytes": 146100000, "write_bytes": 52700000},
-        "c5/fp32": {"workgroups": 3072, "read_bytes": 1301000000, "write_bytes": 600700000},
+    "ce94aa4378d36d855932b857e8d6a1b12f00cca4360e3e1a1e3fa33d6042d580": {
+        "c2/fp64": {"workgroups": 760, "read_bytes": 241000000, "write_bytes": 111700000},
+        "c2/fp32": {"workgroups": 1000, "read_bytes": 118900000, "write_bytes": 52700000},
+        "c5/fp32": {"workgroups": 4072, "read_bytes": 1309300000, "write_bytes": 596900000},
     },
 }
 
