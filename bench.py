@@ -59,7 +59,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1410_0753_amd", "csrc", "clf_kernels.hip"
 # source they were taken on and by workload; they apply only to a launch of
 # the same workgroup count (segment length).
 TRAFFIC = {
-    "ce94aa4378d36d855932b857e8d6a1b12f00cca4360e3e1a1e3fa33d6042d580": {
+    "769db80a462675768e579592546fccaf8d8f7d6914d468f6e1a865af671f2523": {
         "c2/fp64": {"workgroups": 760, "read_bytes": 241000000, "write_bytes": 111700000},
         "c2/fp32": {"workgroups": 1000, "read_bytes": 118900000, "write_bytes": 52700000},
         "c5/fp32": {"workgroups": 4072, "read_bytes": 1309300000, "write_bytes": 596900000},

@@ -2,8 +2,9 @@
 //
 // The hot path is one fused "march" kernel per time step.  A wavefront owns
 // a tile: a strip of 64 consecutive columns (58 output columns plus a
-// 3-column halo on each side) and a segment of rows.  It walks down the
-// segment one row at a time:
+// 3-column halo on each side) and a segment of rows.  It walks along the
+// segment one row at a time (alternate segment rows in opposite directions,
+// so that neighbouring segments read their shared halo rows together):
 //   * the x-sweep of the row (eq2A) runs across the 64 lanes; the neighbour
 //     values of steps (b), (d) and (e) come from the adjacent lanes, and each
 //     of the three neighbour stages costs one lane of validity on each side,
