@@ -1,0 +1,24 @@
+"""CPU checks of the benchmark script's contract: one GPU only, and the
+calibrated traffic table belongs to the kernel source it ships with (a
+kernel edit needs new FETCH_SIZE / WRITE_SIZE runs; until then bench.py
+reports traffic as null)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_traffic_table_matches_kernel_source():
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.kernel_sha() in bench.TRAFFIC
+    for key, t in bench.TRAFFIC[bench.kernel_sha()].items():
+        assert t["workgroups"] > 0 and t["read_bytes"] > 0 and t["write_bytes"] > 0, key
