@@ -1,6 +1,8 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
 times (autotuned segment, gauges, maxwave every step), plus randomised tiny
 grids (edge cases: 3-node lines, ragged strips and segments)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -34,6 +36,36 @@ def test_full_size_2400x1800_fp64_bitwise(clf, oracle_mod):
     mg = [t.cpu().numpy() for t in g.read_maxwave()]
     mo = o.read_maxwave()
     assert np.array_equal(mg[0], mo[0]) and np.array_equal(mg[1], mo[1])
+
+
+@pytest.mark.skipif(os.environ.get("CLF_LONG_TESTS") != "1",
+                    reason="long run (about a minute of oracle time); set CLF_LONG_TESTS=1")
+def test_full_size_2400x1800_fp64_long_bitwise(clf, oracle_mod):
+    # 2000 steps: the waves reach the coast after about 1000, and a few
+    # hundred initially dry nodes flood and dry again; state, gauges and
+    # maxwave bit for bit
+    case = synth.config2(steps=2000)
+    print("full-size 2400x1800 FP64, 2000 steps", flush=True)
+    g = clf.Solver.from_case(case, gout=10, maxout=1, autotune=1)
+    o = oracle_mod.Oracle.from_case(case, gout=10, maxout=1)
+    for obj in (g, o):
+        obj.set_initial(case.eta0, case.u0, case.v0)
+        obj.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
+    for k in range(4):
+        g.step(500)
+        o.step(500)
+        print("  step", 500 * (k + 1), flush=True)
+    for a, b in zip((t.cpu().numpy() for t in g.raw_state()), o.raw_state()):
+        assert np.array_equal(a, b)
+    assert np.array_equal(g.read_gauges()[0], o.read_gauges()[0])
+    mg = [t.cpu().numpy() for t in g.read_maxwave()]
+    mo = o.read_maxwave()
+    assert np.array_equal(mg[0], mo[0]) and np.array_equal(mg[1], mo[1])
+    # nodes dry at the start that were wet at some step (maxwave is kept
+    # on wet nodes only), so the run did exercise inundation
+    ever = (case.depth <= 0) & ((mg[0] != 0) | (mg[1] != 0))
+    print("  initially dry nodes ever wet:", int(ever.sum()), flush=True)
+    assert ever.sum() > 0
 
 
 def test_full_size_8000x6000_fp32_sampled(clf, oracle_mod):
