@@ -267,11 +267,30 @@ struct P64 {
   // one evaluation; with neither real the value is never used.
   static __device__ __forceinline__ Fx interface(const B& a, bool areal, const Bx& b, bool breal,
                                                  double inv) {
-    const double aw = areal ? a.w : -b.w, ac = areal ? a.c : b.c, aD = areal ? a.D : b.D,
-                 at = areal ? a.t : b.t;
-    const double bw = breal ? b.w : -a.w, bc = breal ? b.c : a.c, bD = breal ? b.D : a.D,
-                 bt = breal ? b.t : a.t;
-    return flux(aw, ac, aD, at, bw, bc, bD, bt, inv);
+    const double aw = areal ? a.w : -b.w, ac = areal ? a.c : b.c;
+    const double bw = breal ? b.w : -a.w, bc = breal ? b.c : a.c;
+    // a ghost copies the node's own d and t, so across a ghost both
+    // differences are exactly zero: select the differences, not the operands
+    const bool both = areal && breal;
+    const double dD = both ? b.D - a.D : 0.0, dt = both ? b.t - a.t : 0.0;
+    Fx f;
+    f.P = qhat_d(aw + ac, aw + 2.0 * ac, bw + bc, bw + 2.0 * bc, dD, inv);
+    f.M = qhat_d(aw - ac, aw - 2.0 * ac, bw - bc, bw - 2.0 * bc, dD, inv);
+    const double s = bw + aw;
+    const double h = 0.5 * s;
+    f.T = (h * dt) * inv;
+    return f;
+  }
+  // qhat with the depth difference given
+  static __device__ __forceinline__ double qhat_d(double la, double xa, double lb, double xb,
+                                                  double dd, double inv) {
+    double s = lb + la;
+    double h = 0.5 * s;
+    double dx = xb - xa;
+    double m = h * dx;
+    double gd = kG * dd;
+    double num = m - gd;
+    return num * inv;
   }
 
   // (d) from the values of the interfaces on each side of the node
@@ -505,11 +524,28 @@ struct P32 {
   }
   static __device__ __forceinline__ Fx interface(const B& a, bool areal, const Bx& b, bool breal,
                                                  float inv) {
-    const float aw = areal ? a.w : -b.w, ac = areal ? a.c : b.c, ae = areal ? a.H : b.H,
-                aD = areal ? a.D : b.D, at = areal ? a.t : b.t;
-    const float bw = breal ? b.w : -a.w, bc = breal ? b.c : a.c, be = breal ? b.H : a.H,
-                bD = breal ? b.D : a.D, bt = breal ? b.t : a.t;
-    return flux(aw, ac, ae, aD, at, bw, bc, be, bD, bt, inv);
+    const float aw = areal ? a.w : -b.w, ac = areal ? a.c : b.c;
+    const float bw = breal ? b.w : -a.w, bc = breal ? b.c : a.c;
+    // across a ghost the surface, depth and tangential differences are zero
+    const bool both = areal && breal;
+    const float de = both ? b.H - a.H : 0.f, dD = both ? b.D - a.D : 0.f,
+                dt = both ? b.t - a.t : 0.f;
+    Fx f;
+    f.P = qpm_d(1.f, aw, ac, bw, bc, de, dD, inv);
+    f.M = qpm_d(-1.f, aw, ac, bw, bc, de, dD, inv);
+    f.T = (0.5f * (bw + aw) * dt) * inv;
+    return f;
+  }
+  // qpm with the surface and depth differences given
+  static __device__ __forceinline__ float qpm_d(float sg, float wa, float ca, float wb, float cb,
+                                                float de, float dD, float inv) {
+    const float sw = wb + wa, dw = wb - wa, sc = cb + ca;
+    const float dh = dD + de;
+    const float lam2 = sw + sg * sc;
+    const float adv = 0.5f * lam2 * dw;
+    const float grav = kGf * de;
+    const float cross = kGf * dh * (sw * __builtin_amdgcn_rcpf(sc));
+    return (adv + grav + sg * cross) * inv;
   }
 
   static __device__ __forceinline__ C stage_cd_shared(const B& c, const Fx& FL, const Fx& FR,
