@@ -59,10 +59,10 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1410_0753_amd", "csrc", "clf_kernels.hip"
 # source they were taken on and by workload; they apply only to a launch of
 # the same workgroup count (segment length).
 TRAFFIC = {
-    "6f3808073b98bee44f17150a37828f66976501a1404e60ed4f88efdaa71f4e7e": {
-        "c2/fp64": {"workgroups": 760, "read_bytes": 240700000, "write_bytes": 110900000},
-        "c2/fp32": {"workgroups": 1000, "read_bytes": 118900000, "write_bytes": 52700000},
-        "c5/fp32": {"workgroups": 4072, "read_bytes": 1308700000, "write_bytes": 597400000},
+    "d44cf94b180d3d937a19a20d24f77790f5815ec7c68062b12333e22cb2825dc5": {
+        "c2/fp64": {"workgroups": 760, "read_bytes": 236100000, "write_bytes": 111300000},
+        "c2/fp32": {"workgroups": 1000, "read_bytes": 115900000, "write_bytes": 52700000},
+        "c5/fp32": {"workgroups": 4072, "read_bytes": 1314800000, "write_bytes": 602300000},
     },
 }
 

@@ -108,6 +108,13 @@ __device__ __forceinline__ void gstore_at(T* base, unsigned boff, T v) {
   *(__attribute__((address_space(1))) T*)((char*)base + boff) = v;
 }
 
+// Wet after (a) and before (b).  A node flooded in (b) carries F_FLD, so a
+// post-(b) view answers this as its post-(a) state did: (b) changes no other
+// node, and a flooded node was dry before it.
+__device__ __forceinline__ bool wet_before_b(int f) {
+  return (f & (F_EX | F_WET | F_FLD)) == (F_EX | F_WET);
+}
+
 // ---------------------------------------------------------------------------
 // FP64 node stages (literal form).
 // ---------------------------------------------------------------------------
@@ -155,11 +162,11 @@ struct P64 {
     if ((c.f & F_EX) && !(c.f & (F_WET | F_FIX)) && !blocked) {
       bool qL = false, qR = false;
       double fL = 0.0, fR = 0.0;
-      if ((l.f & (F_EX | F_WET)) == (F_EX | F_WET)) {
+      if (wet_before_b(l.f)) {
         fL = (l.H - l.D) + c.D;
         qL = fL > p.hmin;
       }
-      if ((r.f & (F_EX | F_WET)) == (F_EX | F_WET)) {
+      if (wet_before_b(r.f)) {
         fR = (r.H - r.D) + c.D;
         qR = fR > p.hmin;
       }
@@ -193,8 +200,14 @@ struct P64 {
 
   // a dry node next to a wet one (flags of the neighbours after (a))
   static __device__ __forceinline__ bool flood_candidate(int f, int fl, int fr) {
-    const int ew = F_EX | F_WET;
-    return (f & F_EX) && !(f & (F_WET | F_FIX)) && (((fl & ew) == ew) || ((fr & ew) == ew));
+    return (f & F_EX) && !(f & (F_WET | F_FIX)) && (wet_before_b(fl) || wet_before_b(fr));
+  }
+  // a post-(b) node as the neighbour of a node in (b): the fields that
+  // neighbour reads are those of its post-(a) state (wet_before_b)
+  static __device__ __forceinline__ A pre_b(const B& b) {
+    A a;
+    a.H = b.H; a.w = b.w; a.t = b.t; a.D = b.D; a.f = b.f; a.pad = 0;
+    return a;
   }
 
   // c = sqrt(g h) on every node: dry nodes hold h = 0 (so c = 0), and c of
@@ -436,11 +449,11 @@ struct P32 {
     if ((c.f & F_EX) && !(c.f & (F_WET | F_FIX)) && !blocked) {
       bool qL = false, qR = false;
       float fL = 0.f, fR = 0.f;
-      if ((l.f & (F_EX | F_WET)) == (F_EX | F_WET)) {
+      if (wet_before_b(l.f)) {
         fL = l.H + c.D;
         qL = fL > p.hmin;
       }
-      if ((r.f & (F_EX | F_WET)) == (F_EX | F_WET)) {
+      if (wet_before_b(r.f)) {
         fR = r.H + c.D;
         qR = fR > p.hmin;
       }
@@ -474,8 +487,12 @@ struct P32 {
   }
 
   static __device__ __forceinline__ bool flood_candidate(int f, int fl, int fr) {
-    const int ew = F_EX | F_WET;
-    return (f & F_EX) && !(f & (F_WET | F_FIX)) && (((fl & ew) == ew) || ((fr & ew) == ew));
+    return (f & F_EX) && !(f & (F_WET | F_FIX)) && (wet_before_b(fl) || wet_before_b(fr));
+  }
+  static __device__ __forceinline__ A pre_b(const B& b) {
+    A a;
+    a.H = b.H; a.w = b.w; a.t = b.t; a.D = b.D; a.f = b.f; a.pad = 0;
+    return a;
   }
 
   static __device__ __forceinline__ void set_c(B& b) { b.c = __builtin_amdgcn_sqrtf(kGf * b.h); }
@@ -715,7 +732,7 @@ __device__ __forceinline__ typename P::C xsweep_row(typename P::A a, typename P:
 // Per-lane y pipeline: rotating register windows of the stages.  Row r is
 // pushed in phase K = (r - first) mod 3; slot indices are compile-time so the
 // windows rotate by renaming, not by moves.  After the push of row r:
-//   a[(K+1)%3], a[(K+2)%3], a[K] = post-(a) rows r-2, r-1, r
+//   a[(K+2)%3], a[K] = post-(a) rows r-1, r (a[(K+1)%3] is not read)
 //   b[(K+1)%3], b[(K+2)%3], b[K] = post-(b) rows r-3, r-2, r-1
 //   c[(K+1)%3], c[(K+2)%3], c[K] = post-(d) rows r-4, r-3, r-2
 //   F[K] = interface values between rows r-2 and r-1
@@ -751,15 +768,19 @@ __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_i
                                            typename P::C& out, typename P::B& ob) {
   typedef typename P::R R;
   constexpr int K1 = (K + 1) % 3, K2 = (K + 2) % 3;
-  // window slots by row: a[K] = r, a[K2] = r - D, a[K1] = r - 2D (likewise b
-  // one row behind a, c two rows behind)
-  constexpr int AL = D > 0 ? K1 : K, AU = D > 0 ? K : K1;
+  // window slots by row: a[K] = r, a[K2] = r - D (likewise b one row behind
+  // a, c two rows behind)
   y.a[K] = a_in;
   P::stage_a(y.a[K], cx.par);
-  // (b) on row r - D (centre a[K2]); the flooding logic runs only when some
-  // lane of the wavefront has a dry node next to a wet one
-  if (__ballot(P::flood_candidate(y.a[K2].f, y.a[AL].f, y.a[AU].f)) != 0)
-    y.b[K] = P::stage_b(y.a[AL], y.a[K2], y.a[AU], cx.par);
+  // (b) on row r - D (centre a[K2]).  Its neighbour behind, row r - 2D, is
+  // read from that row's post-(b) view b[K2] (wet_before_b), so the post-(a)
+  // row dies once (b) has read it.  The flooding logic runs only when some
+  // lane of the wavefront has a dry node next to a wet one.
+  const typename P::A ab = P::pre_b(y.b[K2]);
+  const typename P::A& al = D > 0 ? ab : y.a[K];
+  const typename P::A& au = D > 0 ? y.a[K] : ab;
+  if (__ballot(P::flood_candidate(y.a[K2].f, al.f, au.f)) != 0)
+    y.b[K] = P::stage_b(al, y.a[K2], au, cx.par);
   else
     y.b[K] = P::stage_b_copy(y.a[K2]);
   P::set_c(y.b[K]);
@@ -816,9 +837,8 @@ constexpr int FL_ALL = G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N | G_WALLMODE | G_SO
 // grids whose field arrays exceed 4 GiB: every option, 64-bit addresses
 constexpr int FL_WIDE = FL_ALL | G_WIDE;
 
-// Lower bound on resident waves per SIMD handed to the register allocator.
-// The common FP64 kernel sits one register above the three-wave limit of
-// 168 VGPRs without it; with it one value spills, outside the march loop.
+// Lower bound on resident waves per SIMD handed to the register allocator:
+// it holds the common FP64 kernel within the three-wave limit of 168 VGPRs.
 template <class P, int ORDER, int FL>
 constexpr int kStepWaves() {
   return std::is_same<P, P64>::value && FL == FL_FAST && ORDER == ORD_XY ? 3 : 2;
@@ -1027,11 +1047,16 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
             }
           }
         };
-        for (int i = 0; i < npush; i += 3) {
+        // whole triples in the loop, so that its back edge sees the slots in
+        // one rotation (no register copies); the last 0-2 rows after it
+        int i = 0;
+        for (; i + 3 <= npush; i += 3) {
           body(std::integral_constant<int, 0>(), r_first + D * i);
-          if (i + 1 < npush) body(std::integral_constant<int, 1>(), r_first + D * (i + 1));
-          if (i + 2 < npush) body(std::integral_constant<int, 2>(), r_first + D * (i + 2));
+          body(std::integral_constant<int, 1>(), r_first + D * (i + 1));
+          body(std::integral_constant<int, 2>(), r_first + D * (i + 2));
         }
+        if (i < npush) body(std::integral_constant<int, 0>(), r_first + D * i);
+        if (i + 1 < npush) body(std::integral_constant<int, 1>(), r_first + D * (i + 1));
       };
       if (rev)
         march(std::integral_constant<int, -1>());
