@@ -105,7 +105,9 @@ typedef struct clf_grid {
  * clf_default_params fills every field; change what you need. */
 typedef struct clf_params {
   int32_t precision;        /* CLF_FP64 or CLF_FP32 */
-  double h_min;             /* item ground: flow depth at or below which a node is dry (> 0) */
+  double h_min;             /* item ground: flow depth at or below which a node is dry (> 0);
+                               FP64 grids with h_min below 1e-200 run the general (slower)
+                               step kernel, whose square root handles arguments under 2^-767 */
   double manning_n2;        /* item crough: Manning n^2; 0 disables friction */
   int32_t itopo;            /* item itopo: 1 inundation; 0 vertical wall at depth dwall */
   double dwall;             /* item dwall: nodes shallower than this are land when itopo = 0 */

@@ -26,6 +26,8 @@ enum : int {
   G_SPHSRC = 64,    // tan(lat) continuity source in the y-sweep
   G_FRICTION = 128,
   G_WIDE = 256,     // field arrays above 4 GiB: 64-bit addresses in the step kernel
+  G_TINYH = 512,    // FP64 with h_min below 1e-200: wet depths may need the
+                    // small-argument path of the square root
 };
 
 // kernel orders

@@ -212,7 +212,34 @@ struct P64 {
 
   // c = sqrt(g h) on every node: dry nodes hold h = 0 (so c = 0), and c of
   // a node outside the grid is never used (it is no real neighbour)
-  static __device__ __forceinline__ void set_c(B& b) { b.c = sqrt(kG * b.H); }
+  // c = sqrt(g H).  Wet nodes hold H >= h_min and dry ones H = 0, so where
+  // g h_min >= 2^-767 the argument the sweep uses is 0 or at least that
+  // large, and the square root skips the rescaling of smaller arguments.
+  // Both forms round correctly there and agree bit for bit; grids with a
+  // smaller h_min (G_TINYH) run the general kernel, which keeps the full form.
+  static __device__ __forceinline__ void set_c(B& b, const Par& p) {
+    const double x = kG * b.H;
+    b.c = (p.flags & G_TINYH) ? sqrt(x) : sqrt_large(x);
+  }
+  // Square root of 0 or of x >= 2^-767: an estimate of 1/sqrt(x), one
+  // coupled Newton step on sqrt(x) and 1/(2 sqrt(x)), then two corrections
+  // of sqrt(x) by its residual x - s^2 (Goldschmidt's iteration with a
+  // final correction, as in Markstein's correctly rounded square root).
+  // 0 and +inf are returned unchanged.
+  static __device__ __forceinline__ double sqrt_large(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y;
+    double h = 0.5 * y;
+    const double r = __builtin_fma(-h, g, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    double d = __builtin_fma(-g, g, x);
+    g = __builtin_fma(d, h, g);
+    d = __builtin_fma(-g, g, x);
+    g = __builtin_fma(d, h, g);
+    // class mask: -0 (bit 5), +0 (bit 6), +inf (bit 9)
+    return __builtin_amdgcn_class(x, 0x260) ? x : g;
+  }
 
   static __device__ __forceinline__ Bx bx(const B& b) {
     Bx x;
@@ -495,7 +522,9 @@ struct P32 {
     return a;
   }
 
-  static __device__ __forceinline__ void set_c(B& b) { b.c = __builtin_amdgcn_sqrtf(kGf * b.h); }
+  static __device__ __forceinline__ void set_c(B& b, const Par&) {
+    b.c = __builtin_amdgcn_sqrtf(kGf * b.h);
+  }
 
   static __device__ __forceinline__ Bx bx(const B& b) {
     Bx x;
@@ -707,7 +736,7 @@ __device__ __forceinline__ typename P::C xsweep_row(typename P::A a, typename P:
   } else {
     b = P::stage_b_copy(a);
   }
-  P::set_c(b);
+  P::set_c(b, par);
   typename P::Bx bx = P::bx(b);
   typename P::Bx br = from_next(bx);
   C c;
@@ -783,7 +812,7 @@ __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_i
     y.b[K] = P::stage_b(al, y.a[K2], au, cx.par);
   else
     y.b[K] = P::stage_b_copy(y.a[K2]);
-  P::set_c(y.b[K]);
+  P::set_c(y.b[K], cx.par);
   // (c)+(d) on row rc = r - 2D (centre b[K2]; b[K] = row r - D, b[K1] = row r - 3D)
   constexpr int BL = D > 0 ? K1 : K, BU = D > 0 ? K : K1;
   const int rc = r - 2 * D;
@@ -833,7 +862,7 @@ constexpr int FL_FAST = G_SPHSRC;
 // runup workloads: the common case plus bottom friction
 constexpr int FL_FRIC = G_SPHSRC | G_FRICTION;
 constexpr int FL_ALL = G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N | G_WALLMODE | G_SOLVER1 |
-                       G_SPHSRC | G_FRICTION;
+                       G_SPHSRC | G_FRICTION | G_TINYH;
 // grids whose field arrays exceed 4 GiB: every option, 64-bit addresses
 constexpr int FL_WIDE = FL_ALL | G_WIDE;
 

@@ -733,6 +733,7 @@ static int ctx_create(clf_ctx** out, const clf_grid* g, const double* depth, dou
   if (p->solver == 1) flags |= G_SOLVER1;
   if (p->manning_n2 > 0.0) flags |= G_FRICTION;
   if (wide_offsets(c->nx, c->ny, c->fp32)) flags |= G_WIDE;
+  if (!c->fp32 && p->h_min < 1e-200) flags |= G_TINYH;
   gd.flags = flags;
   gd.maxout = p->maxout;
   gd.H[0] = b + L.f[0]; gd.H[1] = b + L.f[1];

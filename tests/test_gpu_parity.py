@@ -285,6 +285,30 @@ def test_errors(clf):
     assert ei.value.code == -6
 
 
+def test_tiny_h_min_thin_film(clf, oracle_mod):
+    # wet films of 1e-245 m put sqrt(g h) arguments below 2^-767, which only
+    # the general kernel's square root rescales; an h_min below 1e-200 routes
+    # the grid there, and the state stays bitwise equal to the oracle's
+    n = 48
+    x = np.arange(n) * 10.0
+    d = np.full((n, n), 20.0)
+    d[:, :8] = 1e-245 * (1.0 + np.arange(8))[None, :]
+    ii = np.arange(n)
+    eta = 0.3 * np.exp(-0.5 * (((ii[None, :] - 34) / 5.0) ** 2 + ((ii[:, None] - 24) / 5.0) ** 2))
+    eta[:, :12] = 0.0
+    dt = 0.4 * 10.0 / np.sqrt(9.81 * 20.0)
+    g = clf.Solver(x, x, d, dt, ssl_alpha=0.0, h_min=1e-250)
+    o = oracle_mod.Oracle(x, x, d, dt, ssl_alpha=0.0, h_min=1e-250)
+    for obj in (g, o):
+        obj.set_initial(eta)
+    w = g.state()[3].cpu().numpy().astype(bool)
+    assert w[:, :8].all()
+    for k in range(3):
+        g.step(20)
+        o.step(20)
+        _cmp_state(g, o, bitwise=True, what="thin film, %d steps" % (20 * (k + 1)))
+
+
 def test_nonfinite_detected(clf, oracle_mod):
     # six times the Courant limit (allowed by raising cfl_limit) overflows
     # within a few steps; the device flag surfaces as CLF_ENONFINITE at sync
