@@ -825,27 +825,45 @@ __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_i
   // interfaces of rows 0 and ny - 1 are evaluated from rows -1 and ny
   if (rc >= 0 && rc <= cx.ny) iL = cload(cx.yib + rc);
   if (rc >= -1 && rc < cx.ny) iR = cload(cx.yib + rc + 1);
+  // Rows y0 - 1 and ylast + 1 lie outside the segment. Their (c)+(d) values
+  // feed only (e) of the adjacent end row, which reads them only when some
+  // node of that row was flooded in (b) (the ballot before stage_e), so
+  // their update is skipped otherwise. That end row's post-(b) view is b[K]
+  // when the march reaches the edge it starts from, and b[K1] at the edge it
+  // ends on (the push that also finishes the end row). FP64 only: the
+  // issue-bound FP32 kernel loses more to the extra branches than it saves.
+  constexpr bool kEdgeSkip = std::is_same<P, P64>::value;
+  const bool start_edge = kEdgeSkip && (D > 0 ? rc == y0 - 1 : rc == ylast + 1);
+  const bool end_edge = kEdgeSkip && (D > 0 ? rc == ylast + 1 : rc == y0 - 1);
+  bool edge_need = true;
+  if (start_edge) edge_need = __ballot(y.b[K].src != 0) != 0;
+  if (end_edge) edge_need = __ballot(y.b[K1].src != 0) != 0;
   if (!SH || (cx.par.flags & G_SOLVER1)) {
-    y.c[K] = P::stage_cd(P::bx(y.b[BL]), y.b[K2], P::bx(y.b[BU]), iL, iR, iS, tr, cx.par);
+    // rows beyond y0 - 1 and ylast + 1 feed nothing written
+    if ((!kEdgeSkip || (rc >= y0 - 1 && rc <= ylast + 1)) && edge_need)
+      y.c[K] = P::stage_cd(P::bx(y.b[BL]), y.b[K2], P::bx(y.b[BU]), iL, iR, iS, tr, cx.par);
   } else if (D > 0) {
     // the interface above row rc was evaluated by the previous push (as the
     // one below row rc - 1); evaluate the one below and keep it for the next.
     // Rows above y0 - 1 only feed rows above the segment, so their update is
     // skipped (a uniform branch), and of row y0 - 2 only the interface below
-    // it is kept.
-    if (rc >= y0 - 2) {
+    // it is kept. Row y0 - 1 always keeps its interface below (row y0 reads
+    // it); row ylast + 1 is the last row of the march.
+    if (rc >= y0 - 2 && (edge_need || !end_edge)) {
       const typename P::Fx FR =
           P::interface(y.b[K2], is_real(y.b[K2].f), P::bx(y.b[BU]), is_real(y.b[BU].f), iR);
-      if (rc >= y0 - 1) y.c[K] = P::stage_cd_shared(y.b[K2], y.F[K2], FR, iS, tr, cx.par);
+      if (rc >= y0 - 1 && edge_need)
+        y.c[K] = P::stage_cd_shared(y.b[K2], y.F[K2], FR, iS, tr, cx.par);
       y.F[K] = FR;
     }
   } else {
     // mirrored: the interface below row rc came from the previous push;
     // evaluate the one above (rows below ylast + 1 feed nothing written)
-    if (rc <= ylast + 2) {
+    if (rc <= ylast + 2 && (edge_need || !end_edge)) {
       const typename P::Fx FL =
           P::interface(y.b[BL], is_real(y.b[BL].f), P::bx(y.b[K2]), is_real(y.b[K2].f), iL);
-      if (rc <= ylast + 1) y.c[K] = P::stage_cd_shared(y.b[K2], FL, y.F[K2], iS, tr, cx.par);
+      if (rc <= ylast + 1 && edge_need)
+        y.c[K] = P::stage_cd_shared(y.b[K2], FL, y.F[K2], iS, tr, cx.par);
       y.F[K] = FL;
     }
   }
