@@ -63,6 +63,7 @@ TRAFFIC = {
         "c2/fp64": {"workgroups": 760, "read_bytes": 235800000, "write_bytes": 111100000},
         "c2/fp32": {"workgroups": 1000, "read_bytes": 115900000, "write_bytes": 52700000},
         "c5/fp32": {"workgroups": 4072, "read_bytes": 1315400000, "write_bytes": 604100000},
+        "c5/fp64": {"workgroups": 3072, "read_bytes": 2559300000, "write_bytes": 1219900000},
     },
 }
 
