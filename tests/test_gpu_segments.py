@@ -47,6 +47,36 @@ def test_short_segments(clf, oracle_mod, segment, order):
         _bitwise(g, o, "segment %d, %d steps" % (segment, 3 * (k + 1)))
 
 
+@pytest.mark.parametrize("segment", [8, 9, 10, 11])
+def test_runup_across_segment_edges(clf, oracle_mod, segment):
+    # A wave runs up a beach that slopes along y. The shoreline advances one
+    # row at a time from row 20 to row 30, so nodes flood in step (b) of the
+    # y-sweep on the first and last rows of segments (both march
+    # directions). Their limiter (e) reads the rows just outside the segment,
+    # whose update the FP64 kernel runs only in that case.
+    nx, ny = 70, 48
+    x = np.arange(nx) * 100.0
+    y = np.arange(ny) * 100.0
+    j = np.arange(ny)[:, None] * np.ones((1, nx))
+    d = 6.0 - 0.3 * j
+    eta = 1.5 * np.exp(-0.5 * ((j - 8) / 3.0) ** 2)
+    v = np.sqrt(9.81 / np.maximum(d, 1.0)) * eta
+    u = np.zeros_like(eta)
+    dt = 0.4 * 100.0 / np.sqrt(9.81 * 8.0)
+    print("segment", segment, flush=True)
+    g = clf.Solver(x, y, d, dt, ssl_alpha=0.0, h_min=0.01, segment=segment)
+    o = oracle_mod.Oracle(x, y, d, dt, ssl_alpha=0.0, h_min=0.01)
+    assert g.query(clf.Q_SEGMENT) == segment
+    for obj in (g, o):
+        obj.set_initial(eta, u, v)
+    for k in range(10):
+        g.step(10)
+        o.step(10)
+        _bitwise(g, o, "runup, segment %d, %d steps" % (segment, 10 * (k + 1)))
+    # the front crossed the edge rows of every segment length above
+    assert np.where(o.state()[3].astype(bool).any(axis=1))[0].max() >= 29
+
+
 @pytest.mark.parametrize("nx", [57, 58, 59, 116, 117, 175])
 def test_strip_widths(clf, oracle_mod, nx):
     case = synth.random_small(14, nx, 23, land=True)
