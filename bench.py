@@ -56,14 +56,17 @@ WORDS_PER_CELL_STEP = 11
 KERNEL_SRC = os.path.join(ROOT, "paper_1410_0753_amd", "csrc", "clf_kernels.hip")
 # Calibrated HBM bytes per launch of the step kernel, from rocprofv3 --pmc
 # FETCH_SIZE / WRITE_SIZE runs (profiles/), keyed by the sha256 of the kernel
-# source they were taken on and by workload; they apply only to a launch of
-# the same workgroup count (segment length).
+# source they were taken on and by workload, one entry per measured launch
+# shape; an entry applies only to a launch of the same workgroup count
+# (segment length), which the autotuner may choose differently run to run.
 TRAFFIC = {
-    "abe132932dce50b44eb344d214f787790deae1524decf5fb5fc88d441ecb6bb7": {
-        "c2/fp64": {"workgroups": 760, "read_bytes": 235800000, "write_bytes": 111100000},
-        "c2/fp32": {"workgroups": 1000, "read_bytes": 115900000, "write_bytes": 52700000},
-        "c5/fp32": {"workgroups": 4072, "read_bytes": 1315400000, "write_bytes": 604100000},
-        "c5/fp64": {"workgroups": 3072, "read_bytes": 2559300000, "write_bytes": 1219900000},
+    "3a945383c5c3f85589fdeeefa4716878974c7d1cb85755825cc2bcf42c25006a": {
+        "c2/fp64": [{"workgroups": 760, "read_bytes": 235700000, "write_bytes": 111100000}],
+        "c2/fp32": [{"workgroups": 1000, "read_bytes": 115900000, "write_bytes": 52700000}],
+        "c5/fp32": [{"workgroups": 4072, "read_bytes": 1314700000, "write_bytes": 602800000},
+                    {"workgroups": 4320, "read_bytes": 1325100000, "write_bytes": 603200000}],
+        "c5/fp64": [{"workgroups": 3072, "read_bytes": 2541800000, "write_bytes": 1219100000},
+                    {"workgroups": 2280, "read_bytes": 2554600000, "write_bytes": 1226400000}],
     },
 }
 
@@ -435,8 +438,9 @@ def main():
     copy_bw = None if args.profile else copy_bandwidth()
     tkey = "%s/%s" % (args.workload, args.precision)
     traffic = None
-    tr = TRAFFIC.get(kernel_sha(), {}).get(tkey)
-    if tr and tr["workgroups"] == head["workgroups"]:
+    tr = next((t for t in TRAFFIC.get(kernel_sha(), {}).get(tkey, [])
+               if t["workgroups"] == head["workgroups"]), None)
+    if tr:
         tb = tr["read_bytes"] + tr["write_bytes"]
         traffic = {"GBps": tb / (head["kernel_ms"] * 1e-3) / 1e9,
                    "bytes_per_launch": tb, "read_bytes": tr["read_bytes"],

@@ -879,9 +879,14 @@ __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_i
 constexpr int FL_FAST = G_SPHSRC;
 // runup workloads: the common case plus bottom friction
 constexpr int FL_FRIC = G_SPHSRC | G_FRICTION;
+// grids driven by boundary forcing (a forcing ring), with or without friction
+constexpr int FL_RING = FL_FRIC | G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N;
 constexpr int FL_ALL = G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N | G_WALLMODE | G_SOLVER1 |
                        G_SPHSRC | G_FRICTION | G_TINYH;
-// grids whose field arrays exceed 4 GiB: every option, 64-bit addresses
+// grids whose field arrays exceed 4 GiB: the same three flag sets with
+// 64-bit addresses
+constexpr int FL_FAST_WIDE = FL_FAST | G_WIDE;
+constexpr int FL_FRIC_WIDE = FL_FRIC | G_WIDE;
 constexpr int FL_WIDE = FL_ALL | G_WIDE;
 
 // Lower bound on resident waves per SIMD handed to the register allocator:
@@ -900,10 +905,14 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
   typedef typename P::A A;
   typedef typename P::C C;
   // Each interface is evaluated once and handed to the node on its other
-  // side, except in the y pipeline of the FP64 friction variants: there the
+  // side, except in the y pipeline of the FP64 friction variants and of the
+  // general variants (both forms give the same bits). In the first, the
   // carried interface values would raise register use past the three
-  // resident waves per SIMD, so each node evaluates both of its interfaces.
-  constexpr bool kShY = !(std::is_same<P, P64>::value && (FL & G_FRICTION) != 0);
+  // resident waves per SIMD. In the second, solver1 takes the per-node form
+  // at run time, and with both forms in one kernel the FP32 pipeline
+  // windows were left in scratch memory (four times slower).
+  constexpr bool kShY = !(std::is_same<P, P64>::value && (FL & G_FRICTION) != 0) &&
+                        (FL & G_SOLVER1) == 0;
   const int lane = threadIdx.x & (WAVE - 1);
   // the wave index is uniform across the wavefront: say so, so that the
   // tile, the row counter and the row metrics live in scalar registers
@@ -1388,18 +1397,37 @@ hipError_t launch_step(int fp32, int order, int gflags, const GridDesc* grids, c
                        int ntiles, StepState* st, int parity, int do_max, int nblocks,
                        hipStream_t s) {
   dim3 grid(nblocks), block(WAVE * WAVES_PER_BLOCK);
-  const bool fast = (gflags & ~FL_FAST) == 0;
-  const bool fric = (gflags & ~FL_FRIC) == 0;
+  const int base = gflags & ~G_WIDE;
+  const bool fast = (base & ~FL_FAST) == 0;
+  const bool fric = (base & ~FL_FRIC) == 0;
+  const bool ring = (base & ~FL_RING) == 0;
   if (gflags & G_WIDE) {
-    if (fp32)
-      launch_order<P32, FL_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
-    else
-      launch_order<P64, FL_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+    if (fp32) {
+      if (fast)
+        launch_order<P32, FL_FAST_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                        do_max);
+      else if (fric)
+        launch_order<P32, FL_FRIC_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                        do_max);
+      else
+        launch_order<P32, FL_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+    } else {
+      if (fast)
+        launch_order<P64, FL_FAST_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                        do_max);
+      else if (fric)
+        launch_order<P64, FL_FRIC_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                        do_max);
+      else
+        launch_order<P64, FL_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+    }
   } else if (fp32) {
     if (fast)
       launch_order<P32, FL_FAST>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
     else if (fric)
       launch_order<P32, FL_FRIC>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+    else if (ring)
+      launch_order<P32, FL_RING>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
     else
       launch_order<P32, FL_ALL>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
   } else {
@@ -1407,6 +1435,8 @@ hipError_t launch_step(int fp32, int order, int gflags, const GridDesc* grids, c
       launch_order<P64, FL_FAST>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
     else if (fric)
       launch_order<P64, FL_FRIC>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+    else if (ring)
+      launch_order<P64, FL_RING>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
     else
       launch_order<P64, FL_ALL>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
   }
@@ -1434,15 +1464,28 @@ static hipError_t occupancy_of(int order, int* n) {
 
 hipError_t step_blocks_per_cu(int fp32, int order, int gflags, int* n) {
   *n = 0;
-  const bool fast = (gflags & ~FL_FAST) == 0;
-  const bool fric = (gflags & ~FL_FRIC) == 0;
-  if (gflags & G_WIDE)
-    return fp32 ? occupancy_of<P32, FL_WIDE>(order, n) : occupancy_of<P64, FL_WIDE>(order, n);
+  const int base = gflags & ~G_WIDE;
+  const bool fast = (base & ~FL_FAST) == 0;
+  const bool fric = (base & ~FL_FRIC) == 0;
+  const bool ring = (base & ~FL_RING) == 0;
+  if (gflags & G_WIDE) {
+    if (fp32)
+      return fast ? occupancy_of<P32, FL_FAST_WIDE>(order, n)
+                  : (fric ? occupancy_of<P32, FL_FRIC_WIDE>(order, n)
+                          : occupancy_of<P32, FL_WIDE>(order, n));
+    return fast ? occupancy_of<P64, FL_FAST_WIDE>(order, n)
+                : (fric ? occupancy_of<P64, FL_FRIC_WIDE>(order, n)
+                        : occupancy_of<P64, FL_WIDE>(order, n));
+  }
   if (fp32)
     return fast ? occupancy_of<P32, FL_FAST>(order, n)
-                : (fric ? occupancy_of<P32, FL_FRIC>(order, n) : occupancy_of<P32, FL_ALL>(order, n));
+                : fric ? occupancy_of<P32, FL_FRIC>(order, n)
+                       : ring ? occupancy_of<P32, FL_RING>(order, n)
+                              : occupancy_of<P32, FL_ALL>(order, n);
   return fast ? occupancy_of<P64, FL_FAST>(order, n)
-              : (fric ? occupancy_of<P64, FL_FRIC>(order, n) : occupancy_of<P64, FL_ALL>(order, n));
+              : fric ? occupancy_of<P64, FL_FRIC>(order, n)
+                     : ring ? occupancy_of<P64, FL_RING>(order, n)
+                            : occupancy_of<P64, FL_ALL>(order, n);
 }
 
 #define CLF_SMALL_LAUNCH(KERNEL, N, ...)                                           \

@@ -20,5 +20,7 @@ def test_traffic_table_matches_kernel_source():
     sys.path.insert(0, ROOT)
     import bench
     assert bench.kernel_sha() in bench.TRAFFIC
-    for key, t in bench.TRAFFIC[bench.kernel_sha()].items():
-        assert t["workgroups"] > 0 and t["read_bytes"] > 0 and t["write_bytes"] > 0, key
+    for key, entries in bench.TRAFFIC[bench.kernel_sha()].items():
+        assert entries, key
+        for t in entries:
+            assert t["workgroups"] > 0 and t["read_bytes"] > 0 and t["write_bytes"] > 0, key

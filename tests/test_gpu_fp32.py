@@ -95,6 +95,27 @@ def test_fp32_options_close_to_oracle(clf, oracle_mod, opts):
     assert r["max_eta_err"] <= 2e-3 and r["mask_flip"] <= 2e-3
 
 
+def test_fp32_forcing_close_to_oracle(clf, oracle_mod):
+    # boundary forcing on all four sides (the forcing-ring kernel variant)
+    case = synth.random_small(10, 64, 48, land=False)
+    t = np.array([0.0, 3 * case.dt, 11 * case.dt])
+    rng = np.random.default_rng(0)
+    g = clf.Solver.from_case(case, precision=clf.FP32, forcing_capacity=8)
+    o = oracle_mod.Oracle.from_case(case)
+    for obj in (g, o):
+        obj.set_initial(case.eta0)
+    for side in range(4):
+        np_ = case.ny if side < 2 else case.nx
+        vals = synth.f32(0.05 * rng.standard_normal((len(t), 3, np_)))
+        g.set_boundary_forcing(side, t, vals)
+        o.set_boundary_forcing(side, t, vals)
+    g.step(15)
+    o.step(15)
+    r = fp32_report(g, o)
+    print(r)
+    assert r["max_eta_err"] <= 2e-3 and r["mask_flip"] <= 2e-3
+
+
 def test_fp32_sampling_runs(clf, oracle_mod):
     case = synth.config1(nx=120, ny=100, steps=10)
     g = clf.Solver.from_case(case, precision=clf.FP32, gout=2)
