@@ -879,8 +879,9 @@ __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_i
 constexpr int FL_FAST = G_SPHSRC;
 // runup workloads: the common case plus bottom friction
 constexpr int FL_FRIC = G_SPHSRC | G_FRICTION;
-// grids driven by boundary forcing (a forcing ring), with or without friction
-constexpr int FL_RING = FL_FRIC | G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N;
+// grids driven by boundary forcing (a forcing ring), without and with friction
+constexpr int FL_RING = FL_FAST | G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N;
+constexpr int FL_RING_FRIC = FL_RING | G_FRICTION;
 constexpr int FL_ALL = G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N | G_WALLMODE | G_SOLVER1 |
                        G_SPHSRC | G_FRICTION | G_TINYH;
 // grids whose field arrays exceed 4 GiB: the same three flag sets with
@@ -1401,6 +1402,7 @@ hipError_t launch_step(int fp32, int order, int gflags, const GridDesc* grids, c
   const bool fast = (base & ~FL_FAST) == 0;
   const bool fric = (base & ~FL_FRIC) == 0;
   const bool ring = (base & ~FL_RING) == 0;
+  const bool ring_fric = (base & ~FL_RING_FRIC) == 0;
   if (gflags & G_WIDE) {
     if (fp32) {
       if (fast)
@@ -1428,6 +1430,9 @@ hipError_t launch_step(int fp32, int order, int gflags, const GridDesc* grids, c
       launch_order<P32, FL_FRIC>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
     else if (ring)
       launch_order<P32, FL_RING>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+    else if (ring_fric)
+      launch_order<P32, FL_RING_FRIC>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                    do_max);
     else
       launch_order<P32, FL_ALL>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
   } else {
@@ -1437,6 +1442,9 @@ hipError_t launch_step(int fp32, int order, int gflags, const GridDesc* grids, c
       launch_order<P64, FL_FRIC>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
     else if (ring)
       launch_order<P64, FL_RING>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+    else if (ring_fric)
+      launch_order<P64, FL_RING_FRIC>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                    do_max);
     else
       launch_order<P64, FL_ALL>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
   }
@@ -1468,6 +1476,7 @@ hipError_t step_blocks_per_cu(int fp32, int order, int gflags, int* n) {
   const bool fast = (base & ~FL_FAST) == 0;
   const bool fric = (base & ~FL_FRIC) == 0;
   const bool ring = (base & ~FL_RING) == 0;
+  const bool ring_fric = (base & ~FL_RING_FRIC) == 0;
   if (gflags & G_WIDE) {
     if (fp32)
       return fast ? occupancy_of<P32, FL_FAST_WIDE>(order, n)
@@ -1479,13 +1488,15 @@ hipError_t step_blocks_per_cu(int fp32, int order, int gflags, int* n) {
   }
   if (fp32)
     return fast ? occupancy_of<P32, FL_FAST>(order, n)
-                : fric ? occupancy_of<P32, FL_FRIC>(order, n)
-                       : ring ? occupancy_of<P32, FL_RING>(order, n)
-                              : occupancy_of<P32, FL_ALL>(order, n);
+                : fric      ? occupancy_of<P32, FL_FRIC>(order, n)
+                : ring      ? occupancy_of<P32, FL_RING>(order, n)
+                : ring_fric ? occupancy_of<P32, FL_RING_FRIC>(order, n)
+                            : occupancy_of<P32, FL_ALL>(order, n);
   return fast ? occupancy_of<P64, FL_FAST>(order, n)
-              : fric ? occupancy_of<P64, FL_FRIC>(order, n)
-                     : ring ? occupancy_of<P64, FL_RING>(order, n)
-                            : occupancy_of<P64, FL_ALL>(order, n);
+              : fric      ? occupancy_of<P64, FL_FRIC>(order, n)
+              : ring      ? occupancy_of<P64, FL_RING>(order, n)
+              : ring_fric ? occupancy_of<P64, FL_RING_FRIC>(order, n)
+                          : occupancy_of<P64, FL_ALL>(order, n);
 }
 
 #define CLF_SMALL_LAUNCH(KERNEL, N, ...)                                           \
