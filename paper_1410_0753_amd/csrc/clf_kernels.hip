@@ -879,8 +879,11 @@ __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_i
 constexpr int FL_FAST = G_SPHSRC;
 // runup workloads: the common case plus bottom friction
 constexpr int FL_FRIC = G_SPHSRC | G_FRICTION;
-// grids driven by boundary forcing (a forcing ring), without and with friction
-constexpr int FL_RING = FL_FAST | G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N;
+// grids driven by boundary forcing (a forcing ring), without and with
+// friction. These sets also take wall mode, which changes only step (b) in
+// the ballot-guarded flooding branch (in the common set the extra code
+// alone cost 0.5-0.8%).
+constexpr int FL_RING = FL_FAST | G_WALLMODE | G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N;
 constexpr int FL_RING_FRIC = FL_RING | G_FRICTION;
 constexpr int FL_ALL = G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N | G_WALLMODE | G_SOLVER1 |
                        G_SPHSRC | G_FRICTION | G_TINYH;
