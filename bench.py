@@ -71,6 +71,14 @@ TRAFFIC = {
 }
 
 
+def traffic_entry(sha, key, workgroups):
+    """The calibrated traffic of a launch of `workgroups` workgroups of the
+    kernel source `sha` on workload `key`, or None when it was not measured
+    (another source, workload or launch shape)."""
+    return next((t for t in TRAFFIC.get(sha, {}).get(key, [])
+                 if t["workgroups"] == workgroups), None)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -436,10 +444,9 @@ def main():
     case = make_case(args.workload, args.steps)
     head = run_grid(case, prec, args.steps, args.warmup)
     copy_bw = None if args.profile else copy_bandwidth()
-    tkey = "%s/%s" % (args.workload, args.precision)
     traffic = None
-    tr = next((t for t in TRAFFIC.get(kernel_sha(), {}).get(tkey, [])
-               if t["workgroups"] == head["workgroups"]), None)
+    tr = traffic_entry(kernel_sha(), "%s/%s" % (args.workload, args.precision),
+                       head["workgroups"])
     if tr:
         tb = tr["read_bytes"] + tr["write_bytes"]
         traffic = {"GBps": tb / (head["kernel_ms"] * 1e-3) / 1e9,

@@ -24,3 +24,16 @@ def test_traffic_table_matches_kernel_source():
         assert entries, key
         for t in entries:
             assert t["workgroups"] > 0 and t["read_bytes"] > 0 and t["write_bytes"] > 0, key
+
+
+def test_traffic_entry_matches_shape_and_source():
+    sys.path.insert(0, ROOT)
+    import bench
+    sha = bench.kernel_sha()
+    for key, entries in bench.TRAFFIC[sha].items():
+        for e in entries:
+            assert bench.traffic_entry(sha, key, e["workgroups"]) is e
+        # a launch shape that was not measured, another source, another workload
+        assert bench.traffic_entry(sha, key, 1 + max(e["workgroups"] for e in entries)) is None
+        assert bench.traffic_entry("0" * 64, key, entries[0]["workgroups"]) is None
+    assert bench.traffic_entry(sha, "no/such", 760) is None
