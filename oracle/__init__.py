@@ -17,11 +17,16 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cliffs_oracle.cpp")
 _LIB = os.path.join(_HERE, "_build", "libcliffs_oracle.so")
+# A prebuilt copy of the oracle to load instead (used by the mutation tests,
+# which compile the oracle with one planted mistake and expect a pin to fail).
+_LIB_OVERRIDE = os.environ.get("CLF_ORACLE_LIB")
 _lock = threading.Lock()
 _lib = None
 
 CARTESIAN, SPHERICAL = 0, 1
 ORDER_XY, ORDER_ALTERNATE = 0, 1
+FRICTION_EXPLICIT, FRICTION_SEMI_IMPLICIT = 0, 1
+OPEN_W, OPEN_E, OPEN_S, OPEN_N = 1, 2, 4, 8
 G = 9.81
 R_EARTH = 6371000.0
 
@@ -46,12 +51,13 @@ def lib():
     global _lib
     with _lock:
         if _lib is None:
-            L = C.CDLL(build())
+            L = C.CDLL(_LIB_OVERRIDE or build())
             L.ora_create.restype = C.c_void_p
             L.ora_create.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, C.c_double,
                                      C.c_double, C.c_double, C.c_int, C.c_double, C.c_double,
                                      C.c_double, C.c_int, C.c_int, C.c_double, C.c_int,
-                                     C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
+                                     C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                     C.POINTER(C.c_int)]
             L.ora_destroy.argtypes = [C.c_void_p]
             L.ora_set_threads.argtypes = [C.c_int]
             L.ora_cs_record_loss.argtypes = [C.c_void_p] + [_dp] * 6 + [
@@ -111,7 +117,7 @@ class Oracle:
     def __init__(self, x, y, depth, dt, coord=CARTESIAN, h_min=0.1, manning_n2=0.0,
                  itopo=1, dwall=0.0, ssl_alpha=2.0, ssl_min_depth=0.1, order=ORDER_XY,
                  solver=2, earth_radius=R_EARTH, spherical_metric=1, maxout=1, gout=1,
-                 bndout=1, sweep_order=None, **device_only):
+                 bndout=1, sweep_order=None, friction_form=0, open_sides=0, **device_only):
         # capacities and limits of the GPU library have no meaning here
         unknown = set(device_only) - {"precision", "cfl_limit", "max_gauges", "gauge_capacity",
                                       "max_enclosed", "max_enclosed_points", "series_capacity",
@@ -127,7 +133,8 @@ class Oracle:
         st = C.c_int(0)
         self._h = L.ora_create(self.nx, self.ny, coord, self.x, self.y, depth, dt, h_min,
                                manning_n2, itopo, dwall, ssl_alpha, ssl_min_depth, order, solver,
-                               earth_radius, spherical_metric, maxout, gout, bndout, C.byref(st))
+                               earth_radius, spherical_metric, maxout, gout, bndout,
+                               int(friction_form), int(open_sides), C.byref(st))
         if not self._h:
             raise ValueError("oracle init failed (status %d)" % st.value)
         self.dt = dt
@@ -138,6 +145,7 @@ class Oracle:
     def from_case(cls, case, **kw):
         kw.setdefault("h_min", case.h_min)
         kw.setdefault("manning_n2", getattr(case, "manning_n2", 0.0))
+        kw.setdefault("friction_form", getattr(case, "friction_form", 0))
         return cls(case.x, case.y, case.depth, case.dt, coord=case.coord, **kw)
 
     def __del__(self):

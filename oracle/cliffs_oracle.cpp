@@ -27,6 +27,11 @@
 // out; flooding ties; direction-aware velocity cap; H = max(P-M,0)^2/16g;
 // arc-length spherical spacing with a tan(lat) continuity source; linear
 // time interpolation of forcing; bilinear wet-weighted nesting output).
+// Bottom friction is the -alpha_j dt term that solver2 and solver1 carry on
+// p and q, with alpha the Manning acceleration g n^2 w |U| / h^(4/3) taken at
+// the old time level like every other right-hand-side term (ptaylor); a
+// semi-implicit form is kept as an option.  Open (radiating) edges are an
+// addition of this repository, not in the paper (see open_ghost).
 //
 // Floating-point order.  Every expression is written with explicit
 // parentheses in the order fixed by the formulation note, compiled with
@@ -36,12 +41,16 @@
 // Parity status: pinned by the CPU test-suite (lake at rest, linear
 // single-node pulse closed forms eq:u/eq:et and eq:u2/eq:et2, Lax-Wendroff
 // Fourier factor, wave speed sqrt(gH), CFL threshold, mirror symmetry,
-// transposition, 1-D reduction, wet-front advance, preprocessing
-// postcondition, restart, complex-step vs finite differences).  The paper
-// gives no spherical equations; the spherical form is pinned by the lake at
-// rest, the equator limit and the first-order convergence of the
-// area-weighted volume sum(h cos(lat)), which the tan(lat) continuity source
-// decides.  The momentum equations carry no spherical terms (none pinned).
+// transposition, 1-D reduction, wet-front advance, flooding tie on a
+// symmetric sill, preprocessing postcondition, sea-floor deformation,
+// friction's one-step closed form and first-order convergence to the decay
+// law, open-edge transparency and drainage, restart, complex-step vs finite
+// differences).  The paper gives no spherical equations; the spherical form
+// is pinned by the lake at rest, the equator limit, the zonal wave speed at
+// 45 N (the cos(lat) factor of the x spacing) and the first-order
+// convergence of the area-weighted volume sum(h cos(lat)), which the
+// tan(lat) continuity source decides.  The momentum equations carry no
+// spherical terms (none pinned).
 
 #include <algorithm>
 #include <cmath>
@@ -72,6 +81,8 @@ struct Par {
   int itopo, solver, order, sph_metric;
   double dwall;
   int maxout, gout, bndout;
+  int fric_form;   // 0: explicit -alpha dt on p and q (solver2); 1: semi-implicit option
+  int open_mask;   // open (radiating) edges: 1 W, 2 E, 4 S, 8 N
 };
 
 // ---------------------------------------------------------------------------
@@ -199,9 +210,35 @@ T advance(const Par& p, const T& xi, const T& lam, const T& QL, const T& QR, con
   return a3 + b4;
 }
 
+// Open (radiating) edge, a reading of this repository (the paper has no open
+// boundary): the neighbour beyond an open edge is a ghost that carries the
+// edge node's outgoing Riemann invariant unchanged and the still-water value
+// of the incoming one.  Beyond the right end the outgoing invariant is
+// p = w + 2c and the incoming one q0 = -2 sqrt(g d); beyond the left end the
+// outgoing one is q = w - 2c and the incoming one p0 = 2 sqrt(g d).  The
+// ghost's velocity and celerity follow from stateu and c = (p - q)/4; its
+// depth and tangential velocity are the edge node's.
+template <class T>
+void open_ghost(const T& w, const T& c, double D, bool right, T* wg, T* cg) {
+  const double c0 = std::sqrt(kG * (D > 0.0 ? D : 0.0));
+  T pp, qq;
+  if (right) {
+    pp = w + 2.0 * c;
+    qq = T(-2.0 * c0);
+  } else {
+    pp = T(2.0 * c0);
+    qq = w - 2.0 * c;
+  }
+  *wg = 0.5 * (pp + qq);
+  T cc = 0.25 * (pp - qq);
+  if (re(cc) < 0.0) cc = T(0.0);
+  *cg = cc;
+}
+
 template <class T>
 void sweep_line(const Par& p, int n, T* H, T* w, T* t, const double* D, const unsigned char* fixed,
-                const double* ib, const double* isb, double fac, const double* tanR) {
+                const double* ib, const double* isb, double fac, const double* tanR,
+                bool open_l, bool open_r) {
   std::vector<char> wet0(n), wet1(n);
   std::vector<int> src(n, 0);  // -1 from left, +1 from right, 2 tie, 0 none
   std::vector<T> H1(n), w1(n), t1(n), Hn(n), wn(n), tn(n);
@@ -272,20 +309,30 @@ void sweep_line(const Par& p, int n, T* H, T* w, T* t, const double* D, const un
     }
     Nb<T> L, C, Rr;
     C.H = H1[k]; C.w = w1[k]; C.t = t1[k]; C.D = D[k];
+    T cC = sqrt_t(kG * C.H), cL, cR;
     if (k > 0 && wet1[k - 1]) {
       L.H = H1[k - 1]; L.w = w1[k - 1]; L.t = t1[k - 1]; L.D = D[k - 1];
+      cL = sqrt_t(kG * L.H);
+    } else if (k == 0 && open_l) {
+      L.H = C.H; L.t = C.t; L.D = C.D;  // open edge ghost (only w and c are used)
+      open_ghost(C.w, cC, C.D, false, &L.w, &cL);
     } else {
       L.H = C.H; L.w = -C.w; L.t = C.t; L.D = C.D;  // mirror ghost
+      cL = cC;
     }
     if (k + 1 < n && wet1[k + 1]) {
       Rr.H = H1[k + 1]; Rr.w = w1[k + 1]; Rr.t = t1[k + 1]; Rr.D = D[k + 1];
+      cR = sqrt_t(kG * Rr.H);
+    } else if (k == n - 1 && open_r) {
+      Rr.H = C.H; Rr.t = C.t; Rr.D = C.D;
+      open_ghost(C.w, cC, C.D, true, &Rr.w, &cR);
     } else {
       Rr.H = C.H; Rr.w = -C.w; Rr.t = C.t; Rr.D = C.D;
+      cR = cC;
     }
     const double iL = fac * ib[k];
     const double iR = fac * ib[k + 1];
     const double iS = fac * isb[k];
-    T cC = sqrt_t(kG * C.H), cL = sqrt_t(kG * L.H), cR = sqrt_t(kG * Rr.H);
     // family P: xi = w + 2c, lambda = w + c
     T xP_L = L.w + 2.0 * cL, xP_C = C.w + 2.0 * cC, xP_R = Rr.w + 2.0 * cR;
     T lP_L = L.w + cL, lP_C = C.w + cC, lP_R = Rr.w + cR;
@@ -315,14 +362,25 @@ void sweep_line(const Par& p, int n, T* H, T* w, T* t, const double* D, const un
       Pn = Pn + s3;
       Mn = Mn - s3;
     }
+    if (p.n2 > 0.0 && p.fric_form == 0) {
+      // bottom friction, the -alpha_j dt term of solver2 / solver1 on p and q,
+      // with the Manning acceleration alpha = g n^2 w |U| / h^(4/3) at the old
+      // time level
+      T sp = sqrt_t(C.w * C.w + C.t * C.t);
+      T den = C.H * cbrt_t(C.H);
+      T al = ((p.gn2 * C.w) * sp) / den;
+      T a = p.dt * al;
+      Pn = Pn - a;
+      Mn = Mn - a;
+    }
     // stateu, stateh
     T ws = Pn + Mn;
     T wv = 0.5 * ws;
     T dd = Pn - Mn;
     if (re(dd) < 0.0) dd = zero;
     T Hv = (dd * dd) * p.inv16g;
-    if (p.n2 > 0.0) {
-      // bottom friction on the normal velocity (semi-implicit Manning)
+    if (p.n2 > 0.0 && p.fric_form == 1) {
+      // option: semi-implicit Manning on the normal velocity, w' / (1 + dt alpha / w)
       T sp = sqrt_t(C.w * C.w + C.t * C.t);
       T den = C.H * cbrt_t(C.H);
       T fr = (p.dt * p.gn2 * sp) / den;
@@ -460,7 +518,8 @@ void xsweep(Model<T>& m) {
       fx[i] = is_fixed(m, i, j);
     }
     sweep_line(m.p, nx, H.data(), w.data(), t.data(), D.data(), fx.data(), m.xib.data(),
-               m.xisb.data(), m.xfac[j], nullptr);
+               m.xisb.data(), m.xfac[j], nullptr, (m.p.open_mask & 1) != 0,
+               (m.p.open_mask & 2) != 0);
     for (int i = 0; i < nx; ++i) {
       size_t k = (size_t)j * nx + i;
       m.H[k] = H[i]; m.u[k] = w[i]; m.v[k] = t[i];
@@ -484,7 +543,8 @@ void ysweep(Model<T>& m) {
       fx[j] = is_fixed(m, i, j);
     }
     sweep_line(m.p, ny, H.data(), w.data(), t.data(), D.data(), fx.data(), m.yib.data(),
-               m.yisb.data(), 1.0, m.coord == 1 ? m.tanR.data() : nullptr);
+               m.yisb.data(), 1.0, m.coord == 1 ? m.tanR.data() : nullptr,
+               (m.p.open_mask & 4) != 0, (m.p.open_mask & 8) != 0);
     for (int j = 0; j < ny; ++j) {
       size_t k = (size_t)j * nx + i;
       m.H[k] = H[j]; m.v[k] = w[j]; m.u[k] = t[j];
@@ -681,8 +741,10 @@ template <class T>
 int init_model(Model<T>& m, int nx, int ny, int coord, const double* x, const double* y,
                const double* depth, double dt, double hmin, double n2, int itopo, double dwall,
                double ssl_alpha, double ssl_min, int order, int solver, double R, int sph,
-               int maxout, int gout, int bndout) {
+               int maxout, int gout, int bndout, int fric_form, int open_mask) {
   if (nx < 1 || ny < 1) return -1;
+  if (fric_form != 0 && fric_form != 1) return -1;
+  if (open_mask < 0 || open_mask > 15) return -1;
   bool oned = nx == 1 || ny == 1;
   if (oned && nx * ny < 3) return -1;
   if (!oned && (nx < 3 || ny < 3)) return -1;
@@ -712,6 +774,8 @@ int init_model(Model<T>& m, int nx, int ny, int coord, const double* x, const do
   p.maxout = maxout;
   p.gout = gout;
   p.bndout = bndout;
+  p.fric_form = fric_form;
+  p.open_mask = open_mask;
   if (ssl_alpha > 0.0) {
     m.ssl_passes = ssl_run(nx, ny, m.d.data(), ssl_alpha, ssl_min);
     if (m.ssl_passes < 0) return -2;
@@ -811,10 +875,10 @@ int ora_set_threads(int n) {
 void* ora_create(int nx, int ny, int coord, const double* x, const double* y, const double* depth,
                  double dt, double hmin, double n2, int itopo, double dwall, double ssl_alpha,
                  double ssl_min, int order, int solver, double R, int sph, int maxout, int gout,
-                 int bndout, int* status) {
+                 int bndout, int fric_form, int open_mask, int* status) {
   OraModel* m = new OraModel();
   int rc = init_model(*m, nx, ny, coord, x, y, depth, dt, hmin, n2, itopo, dwall, ssl_alpha,
-                      ssl_min, order, solver, R, sph, maxout, gout, bndout);
+                      ssl_min, order, solver, R, sph, maxout, gout, bndout, fric_form, open_mask);
   *status = rc;
   if (rc != 0) {
     delete m;

@@ -2,9 +2,9 @@
 // Built with -fsanitize=address,undefined together with cliffs_oracle.cpp and
 // run by tests/test_oracle_sanitized.py: every entry point of the C API is
 // exercised on small grids (Cartesian with land, spherical, 1-D along each
-// axis, friction, solver1, alternate order, wall mode, gauges, enclosed
-// grids, forcing, restart, complex step).  A sanitizer report, or a
-// non-finite result, makes the program exit non-zero.
+// axis, friction in both forms, open edges, solver1, alternate order, wall
+// mode, gauges, enclosed grids, forcing, restart, complex step).  A
+// sanitizer report, or a non-finite result, makes the program exit non-zero.
 #include <cmath>
 #include <cstdio>
 #include <vector>
@@ -14,7 +14,7 @@ int ora_set_threads(int n);
 void* ora_create(int nx, int ny, int coord, const double* x, const double* y, const double* depth,
                  double dt, double hmin, double n2, int itopo, double dwall, double ssl_alpha,
                  double ssl_min, int order, int solver, double R, int sph, int maxout, int gout,
-                 int bndout, int* status);
+                 int bndout, int fric_form, int open_mask, int* status);
 void ora_destroy(void* h);
 int ora_ssl_passes(void* h);
 double ora_max_cfl(void* h);
@@ -62,7 +62,7 @@ bool all_finite(const std::vector<double>& a) {
 // One scenario: a basin with a coast on the west, a bump of water, and every
 // output read back.
 void scenario(int nx, int ny, int coord, int solver, int order, double n2, int itopo,
-              bool extras) {
+              bool extras, int fric_form = 0, int open_mask = 0) {
   std::vector<double> x(nx), y(ny), d((size_t)nx * ny), eta((size_t)nx * ny, 0.0);
   const double dx = coord ? 1.0 / 60.0 : 200.0;
   for (int i = 0; i < nx; ++i) x[i] = (coord ? 150.0 : 0.0) + i * dx;
@@ -76,7 +76,8 @@ void scenario(int nx, int ny, int coord, int solver, int order, double n2, int i
     }
   int st = 0;
   void* h = ora_create(nx, ny, coord, x.data(), y.data(), d.data(), coord ? 2.0 : 1.0, 0.1, n2,
-                       itopo, 0.5, 2.0, 0.1, order, solver, 6371000.0, 1, 1, 2, 1, &st);
+                       itopo, 0.5, 2.0, 0.1, order, solver, 6371000.0, 1, 1, 2, 1, fric_form,
+                       open_mask, &st);
   check(h != nullptr && st == 0, "create");
   if (!h) return;
   check(ora_max_cfl(h) < 1.0 && ora_ssl_passes(h) >= 0, "diagnostics");
@@ -129,7 +130,7 @@ void complex_step() {
   for (size_t k = 0; k < eta.size(); ++k) eta[k] = 0.1 * std::sin(0.7 * k);
   int st = 0;
   void* h = ora_create(nx, ny, 0, x.data(), y.data(), d.data(), 1.0, 0.1, 0.0, 1, 0.0, 2.0, 0.1,
-                       0, 2, 6371000.0, 1, 1, 1, 1, &st);
+                       0, 2, 6371000.0, 1, 1, 1, 1, 0, 0, &st);
   std::vector<int> gx = {3, 9}, gy = {4, 7};
   ora_set_gauges(h, 2, gx.data(), gy.data());
   std::vector<double> obs(11 * 2 * 3, 0.0), w = {1.0, 0.5, 0.5};
@@ -149,6 +150,9 @@ int main() {
   scenario(40, 30, 0, 2, 0, 0.0, 1, true);     // Cartesian, land, nesting, forcing
   scenario(40, 30, 1, 2, 1, 0.0, 1, true);     // spherical, alternate order
   scenario(40, 30, 0, 1, 0, 0.0009, 1, false); // solver1, friction
+  scenario(40, 30, 1, 2, 0, 0.0009, 1, false, 1, 0);  // semi-implicit friction option
+  scenario(40, 30, 0, 2, 0, 0.0, 1, false, 0, 15);    // open edges
+  scenario(50, 1, 0, 2, 0, 0.0, 1, false, 0, 3);      // open ends of a 1-D line
   scenario(40, 30, 0, 2, 0, 0.0, 0, false);    // wall mode
   scenario(50, 1, 0, 2, 0, 0.0, 1, false);     // 1-D along x
   scenario(1, 50, 0, 2, 0, 0.0, 1, false);     // 1-D along y

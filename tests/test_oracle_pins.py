@@ -406,24 +406,78 @@ def test_dry_threshold_inclusive(oracle_mod):
     assert o2.state()[3].sum() == n
 
 
-def test_friction_matches_decay_law(oracle_mod):
-    # uniform current on a flat bottom: du/dt = -g n^2 u|u| / h^(4/3), whose
+def test_friction_semi_implicit_option_matches_decay_law(oracle_mod):
+    # The semi-implicit option (friction_form 1, not the paper's form):
+    # uniform current on a flat bottom, du/dt = -g n^2 u|u| / h^(4/3), whose
     # solution is 1/u(t) = 1/u0 + k t, k = g n^2 / h^(4/3).  Far from the walls
-    # the node sees no gradient; the semi-implicit friction step reproduces
-    # the decay law to rounding.
+    # the node sees no gradient; the semi-implicit step reproduces the decay
+    # law to rounding (this checks the option's own identity only).
     n, h, n2, u0, T, dt = 80, 5.0, 0.0009, 0.5, 200.0, 1.0
     k = G * n2 / h ** (4.0 / 3.0)
     x = np.arange(n) * 1000.0
-    o = oracle_mod.Oracle(x, x[:4], np.full((4, n), h), dt, ssl_alpha=0.0, manning_n2=n2)
+    o = oracle_mod.Oracle(x, x[:4], np.full((4, n), h), dt, ssl_alpha=0.0, manning_n2=n2,
+                          friction_form=1)
     o.set_raw_state(np.full((4, n), h), np.full((4, n), u0), np.zeros((4, n)), 0)
     o.step(int(T / dt))
     uu = o.raw_state()[1][2, n // 2]
     assert abs(uu - u0 / (1 + k * u0 * T)) <= 1e-9 * u0
     # friction acts on the normal velocity of each sweep: a current along y decays alike
-    o2 = oracle_mod.Oracle(x[:4], x, np.full((n, 4), h), dt, ssl_alpha=0.0, manning_n2=n2)
+    o2 = oracle_mod.Oracle(x[:4], x, np.full((n, 4), h), dt, ssl_alpha=0.0, manning_n2=n2,
+                           friction_form=1)
     o2.set_raw_state(np.full((n, 4), h), np.zeros((n, 4)), np.full((n, 4), u0), 0)
     o2.step(int(T / dt))
     assert abs(o2.raw_state()[2][n // 2, 2] - u0 / (1 + k * u0 * T)) <= 1e-9 * u0
+
+
+# ---------------------------------------------------------------------------
+# Friction as the paper writes it: the -alpha_j dt term of solver2 (and
+# solver1) on p and q, with every right-hand-side quantity at the old time
+# level (ptaylor), alpha the Manning acceleration g n^2 w |U| / h^(4/3).
+# On a uniform current every Q vanishes, so one sweep gives
+# p1 = p0 - alpha dt, q1 = q0 - alpha dt: u1 = u0 - alpha dt and h unchanged.
+# ---------------------------------------------------------------------------
+def _uniform_current(oracle_mod, h, n2, u0, v0, dt, n=40, form=0):
+    x = np.arange(n) * 1000.0
+    o = oracle_mod.Oracle(x, x[:n], np.full((n, n), h), dt, ssl_alpha=0.0, manning_n2=n2,
+                          friction_form=form)
+    o.set_raw_state(np.full((n, n), h), np.full((n, n), u0), np.full((n, n), v0), 0)
+    return o
+
+
+def test_friction_explicit_one_step(oracle_mod):
+    h, n2, dt = 4.0, 0.0009, 2.0
+    k = G * n2 / h ** (4.0 / 3.0)
+    c = 20                            # interior node, far from the walls
+    # x-sweep then y-sweep: the y-sweep sees the x-updated u in |U|
+    for u0, v0 in ((0.8, 0.0), (0.0, -0.6), (0.7, -0.4)):
+        o = _uniform_current(oracle_mod, h, n2, u0, v0, dt)
+        o.step(1)
+        H1, u1, v1 = (a[c, c] for a in o.raw_state())
+        du = dt * k * u0 * math.hypot(u0, v0)
+        ux = u0 - du
+        dv = dt * k * v0 * math.hypot(ux, v0)
+        assert abs((u0 - u1) - du) <= 1e-9 * max(abs(du), 1e-300) + 1e-15
+        assert abs((v0 - v1) - dv) <= 1e-9 * max(abs(dv), 1e-300) + 1e-15
+        assert abs(H1 - h) <= 1e-12 * h
+    # the semi-implicit option gives u0 / (1 + dt k |U|): a different first step
+    o = _uniform_current(oracle_mod, h, n2, 0.8, 0.0, dt, form=1)
+    o.step(1)
+    u1 = o.raw_state()[1][c, c]
+    assert abs((0.8 - u1) - dt * k * 0.64) > 1e-6 * dt * k * 0.64
+
+
+def test_friction_explicit_converges_to_decay_law(oracle_mod):
+    # explicit in time: first-order convergence to 1/u = 1/u0 + k t
+    h, n2, u0, T = 5.0, 0.0009, 0.5, 200.0
+    k = G * n2 / h ** (4.0 / 3.0)
+    exact = u0 / (1 + k * u0 * T)
+    errs = []
+    for dt in (2.0, 1.0, 0.5):
+        o = _uniform_current(oracle_mod, h, n2, u0, 0.0, dt, n=80)
+        o.step(int(round(T / dt)))
+        errs.append(abs(o.raw_state()[1][40, 40] - exact))
+    assert errs[2] <= 2e-3 * (u0 - exact)
+    assert 1.8 < errs[0] / errs[1] < 2.2 and 1.8 < errs[1] / errs[2] < 2.2
 
 
 def test_two_d_front_respects_sweep_axis(oracle_mod):
@@ -862,3 +916,196 @@ def test_nested_chain(oracle_mod):
     amp = np.abs(ref).max()
     assert amp > 0.01
     assert np.abs(ec[2:-2, 2:-2] - ref[2:-2, 2:-2]).max() <= 0.1 * amp
+
+
+# ---------------------------------------------------------------------------
+# Spherical x spacing (reading of Running Options item 1, geographic
+# coordinates): a zonal, latitude-uniform small wave on constant depth at
+# 45 N travels at sqrt(g H) / (R cos(lat) pi/180) degrees of longitude per
+# second.  Dropping cos(lat), or taking it of the latitude in radians, moves
+# the speed by 41% or more.
+# ---------------------------------------------------------------------------
+def test_spherical_zonal_wave_speed_at_45N(oracle_mod):
+    H, R = 1000.0, 6371000.0
+    c0 = math.sqrt(G * H)
+    nx, ny, dl = 1200, 5, 0.01
+    lon = 150.0 + np.arange(nx) * dl
+    lat = 45.0 + (np.arange(ny) - 2) * dl
+    d = np.full((ny, nx), H)
+    dt = synth.cfl_dt(synth.SPHERICAL, lon, lat, d, cfl=0.8)
+    i0 = 300
+    i = np.arange(nx)
+    eta = (1e-3 * np.exp(-0.5 * ((i - i0) / 10.0) ** 2))[None, :] * np.ones((ny, 1))
+    o = oracle_mod.Oracle(lon, lat, d, dt, coord=synth.SPHERICAL, ssl_alpha=0.0, h_min=1e-3)
+    o.set_initial(eta, eta * math.sqrt(G / H), None)   # right-moving wave
+    N = 600
+    o.step(N)
+    e = o.state()[0][2]
+    k = int(np.argmax(e))
+    ym, y0, yp = e[k - 1], e[k], e[k + 1]
+    kf = k + 0.5 * (ym - yp) / (ym - 2 * y0 + yp)
+    speed = (kf - i0) * dl / (N * dt)
+    expect = c0 / (R * math.cos(math.radians(45.0)) * math.pi / 180.0)
+    assert abs(speed / expect - 1.0) <= 5e-3
+
+
+# ---------------------------------------------------------------------------
+# Sea-floor deformation (Running Options item quake): the deformation moves
+# the bottom, the water column keeps its height, so the depth becomes d - eta
+# and the surface rises by eta over every wet node; a uniform uplift of a
+# closed flat basin leaves the water at rest.
+# ---------------------------------------------------------------------------
+def test_deform_bottom_definition(oracle_mod):
+    c = synth.random_small(21, 30, 24, land=True)
+    o = oracle_mod.Oracle.from_case(c)
+    d0 = o.depth()
+    rng = np.random.default_rng(8)
+    eta = synth.f32(0.4 * rng.standard_normal(d0.shape))
+    o.set_initial(eta, None, None, deform_bottom=True)
+    assert np.array_equal(o.depth(), d0 - eta)
+    e, u, v, w = o.state()
+    wet = d0 > c.h_min
+    assert np.array_equal(w.astype(bool), wet)
+    assert np.abs(e[wet] - eta[wet]).max() <= 1e-13 * np.abs(d0).max()
+    assert (e[~wet] == 0).all()
+    # surface deformation of the same eta gives the same surface, a different depth
+    s = oracle_mod.Oracle.from_case(c)
+    s.set_initial(eta, None, None, deform_bottom=False)
+    assert np.array_equal(s.depth(), d0)
+
+
+def test_deform_bottom_uniform_uplift_stays_at_rest(oracle_mod):
+    n, h = 24, 100.0
+    x = np.arange(n) * 500.0
+    d = np.full((n, n), h)
+    dt = synth.cfl_dt(0, x, x, d, cfl=0.8)
+    o = oracle_mod.Oracle(x, x, d, dt, ssl_alpha=0.0)
+    o.set_initial(np.full((n, n), 0.5), None, None, deform_bottom=True)
+    o.step(300)
+    e, u, v, w = o.state()
+    assert w.all()
+    assert (u == 0).all() and (v == 0).all()
+    assert np.abs(e - 0.5).max() <= 1e-12 * h
+
+
+# ---------------------------------------------------------------------------
+# Flooding tie (Inundation algorithm step (b), reading: when both neighbours
+# qualify equally the flooded node takes the mean of their velocities and the
+# (e) cap uses the smaller neighbour).  Two mirror-image waves reach a dry
+# sill in the same sweep: the sill floods by the tie rule (its velocity is
+# exactly zero by symmetry) and the whole run stays mirror-symmetric to the
+# bit.  Taking either side's velocity instead breaks both.
+# ---------------------------------------------------------------------------
+def _sill_case(n=41, sill=-0.3, slope=1.0, deep=10.0, dx=50.0, amp=1.0):
+    j = np.arange(n)
+    jc = n // 2
+    d = np.minimum(deep, sill + slope * np.abs(j - jc)).astype(np.float64)
+    x = np.arange(n) * dx
+    sig = 3.0
+    e = amp * (np.exp(-0.5 * ((j - jc + 12) / sig) ** 2) + np.exp(-0.5 * ((j - jc - 12) / sig) ** 2))
+    c = np.sqrt(G * np.maximum(d, 0.0) / 1.0)
+    u = np.where(j < jc, 1.0, -1.0) * e * np.sqrt(G / np.maximum(d, 1.0))
+    u[jc] = 0.0
+    e = np.where(d > 0, e, 0.0)
+    u = np.where(d > 0, u, 0.0)
+    dt = 0.4 * dx / math.sqrt(G * (deep + 2 * amp))
+    return x, d, synth.f32(e), synth.f32(u), dt
+
+
+def _tie_run(oracle_mod, axis, steps=40):
+    x, d, e, u, dt = _sill_case()
+    n, jc = len(x), len(x) // 2
+    one = np.array([0.0])
+    if axis == 0:
+        o = oracle_mod.Oracle(x, one, d[None, :], dt, ssl_alpha=0.0, h_min=0.01)
+        o.set_initial(e[None, :], u[None, :], None)
+    else:
+        o = oracle_mod.Oracle(one, x, d[:, None], dt, ssl_alpha=0.0, h_min=0.01)
+        o.set_initial(e[:, None], None, u[:, None])
+    first_wet = None
+    for s in range(steps):
+        o.step(1)
+        H, uu, vv = (a.reshape(-1) for a in o.raw_state())
+        w = uu if axis == 0 else vv
+        assert np.array_equal(H, H[::-1])
+        assert np.array_equal(w, -w[::-1])
+        if first_wet is None and H[jc] > 0.01:
+            first_wet = s
+            assert w[jc] == 0.0
+    return first_wet
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_flood_tie_on_symmetric_sill(oracle_mod, axis):
+    assert _tie_run(oracle_mod, axis) is not None, "the sill never flooded"
+
+
+# ---------------------------------------------------------------------------
+# Open (radiating) edge, this repository's reading (the paper has none): the
+# ghost beyond the edge carries the outgoing Riemann invariant unchanged and
+# the still-water incoming one.  A linear pulse leaving the domain through an
+# open edge leaves less than 1e-4 of its amplitude behind; through a wall it
+# comes back whole.  A lake at rest stays at rest to the bit.
+# ---------------------------------------------------------------------------
+def _leaving_pulse(oracle_mod, axis, right, open_sides):
+    n, dx, H = 400, 100.0, 100.0
+    c0 = math.sqrt(G * H)
+    dt = 0.8 * dx / c0
+    j = np.arange(n)
+    j0 = 300 if right else 100
+    e = 1e-3 * np.exp(-0.5 * ((j - j0) / 10.0) ** 2)
+    w = (1.0 if right else -1.0) * e * math.sqrt(G / H)
+    x = np.arange(n) * dx
+    one = np.array([0.0, dx, 2 * dx])
+    if axis == 0:
+        o = oracle_mod.Oracle(x, one, np.full((3, n), H), dt, ssl_alpha=0.0, h_min=1e-3,
+                              open_sides=open_sides)
+        o.set_initial(np.tile(e, (3, 1)), np.tile(w, (3, 1)), None)
+    else:
+        o = oracle_mod.Oracle(one, x, np.full((n, 3), H), dt, ssl_alpha=0.0, h_min=1e-3,
+                              open_sides=open_sides)
+        o.set_initial(np.tile(e[:, None], (1, 3)), None, np.tile(w[:, None], (1, 3)))
+    o.step(400)
+    return np.abs(o.state()[0]).max() / 1e-3
+
+
+@pytest.mark.parametrize("axis,right,side", [(0, True, 2), (0, False, 1), (1, True, 8),
+                                             (1, False, 4)])
+def test_open_edge_lets_a_linear_pulse_leave(oracle_mod, axis, right, side):
+    assert _leaving_pulse(oracle_mod, axis, right, side) < 1e-4
+    assert _leaving_pulse(oracle_mod, axis, right, 0) > 0.8
+    # the other side open does not help
+    other = {1: 2, 2: 1, 4: 8, 8: 4}[side]
+    assert _leaving_pulse(oracle_mod, axis, right, other) > 0.8
+
+
+def test_open_edges_keep_a_lake_at_rest(oracle_mod):
+    c = synth.random_small(3, 40, 32, land=False)
+    o = oracle_mod.Oracle.from_case(c, open_sides=15)
+    o.set_initial(None)
+    o.step(500)
+    e, u, v, w = o.state()
+    assert w.all()
+    assert np.abs(e).max() <= 1e-10 and (u == 0).all() and (v == 0).all()
+
+
+def test_open_edge_drains_a_raised_lake_to_still_water(oracle_mod):
+    # the still-water incoming invariant makes the open edge a boundary to a
+    # sea at rest at eta = 0: a uniformly raised basin drains to that level
+    # within a few crossing times; closed by walls it stays raised
+    n, dx, H = 100, 100.0, 10.0
+    dt = 0.8 * dx / math.sqrt(G * H)
+    x = np.arange(n) * dx
+    three = np.array([0.0, dx, 2 * dx])
+    for axis, side in ((0, 2), (0, 1), (1, 8), (1, 4)):
+        xs, ys = (x, three) if axis == 0 else (three, x)
+        shape = (len(ys), len(xs))
+        res = {}
+        for sides in (side, 0):
+            o = oracle_mod.Oracle(xs, ys, np.full(shape, H), dt, ssl_alpha=0.0, h_min=1e-3,
+                                  open_sides=sides)
+            o.set_initial(np.full(shape, 0.05))
+            o.step(400)
+            res[sides] = np.abs(o.state()[0]).max()
+        assert res[side] <= 1e-6 * 0.05
+        assert abs(res[0] - 0.05) <= 1e-12
