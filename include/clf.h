@@ -137,9 +137,25 @@ typedef struct clf_params {
                                replays of a hipGraph holding this many steps (even); 0: off */
   int32_t persistent_blocks; /* >0: the step kernel runs this many workgroups (a multiple of 8)
                                looping over the tiles; 0: one wavefront per tile */
+  int32_t friction_form;    /* bottom friction (manning_n2 > 0): 0 (default) the -alpha_j dt term
+                               of solver2 / solver1 on p and q, alpha = g n^2 w |U| / h^(4/3) at the
+                               old time level; 1 semi-implicit option w' / (1 + dt alpha / w),
+                               unconditionally damping in thin layers */
+  int32_t open_sides;       /* open (radiating) edges, not in the paper: bit mask 1 W, 2 E, 4 S,
+                               8 N.  The ghost beyond an open edge carries the edge node's
+                               outgoing Riemann invariant and the still-water incoming one
+                               (p0 = 2 sqrt(g d) from the west/south, q0 = -2 sqrt(g d) from the
+                               east/north).  Other edges are walls.  Grids with open edges run the
+                               general (slower) step kernel; the adjoint rejects them. */
 } clf_params;
 
 void clf_default_params(clf_params* p);
+
+/* Row-major index iy * nx + ix of node (ix, iy), 0-based, computed in 64 bits
+ * (grids hold up to 2^32 - 1 nodes).  CLF_EINVAL if the node is outside an
+ * nx x ny grid or index is NULL.  Host only; the library indexes gauges this
+ * way. */
+int clf_node_index(int nx, int ny, int ix, int iy, int64_t* index);
 
 /* Device workspace needed by clf_init for this grid and these parameters. */
 int clf_workspace_bytes(const clf_grid* g, const clf_params* p, size_t* bytes);

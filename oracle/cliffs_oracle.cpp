@@ -29,8 +29,9 @@
 // time interpolation of forcing; bilinear wet-weighted nesting output).
 // Bottom friction is the -alpha_j dt term that solver2 and solver1 carry on
 // p and q, with alpha the Manning acceleration g n^2 w |U| / h^(4/3) taken at
-// the old time level like every other right-hand-side term (ptaylor); a
-// semi-implicit form is kept as an option.  Open (radiating) edges are an
+// the old time level like every other right-hand-side term (ptaylor), its
+// decrement capped at the velocity itself (friction does not reverse the
+// flow); a semi-implicit form is kept as an option.  Open (radiating) edges are an
 // addition of this repository, not in the paper (see open_ghost).
 //
 // Floating-point order.  Every expression is written with explicit
@@ -365,11 +366,14 @@ void sweep_line(const Par& p, int n, T* H, T* w, T* t, const double* D, const un
     if (p.n2 > 0.0 && p.fric_form == 0) {
       // bottom friction, the -alpha_j dt term of solver2 / solver1 on p and q,
       // with the Manning acceleration alpha = g n^2 w |U| / h^(4/3) at the old
-      // time level
+      // time level: alpha dt = f w with f = dt g n^2 |U| / h^(4/3).  Friction
+      // cannot reverse the flow, so f is capped at 1 (reading: in thin fast
+      // layers the uncapped explicit term overshoots and grows without bound)
       T sp = sqrt_t(C.w * C.w + C.t * C.t);
       T den = C.H * cbrt_t(C.H);
-      T al = ((p.gn2 * C.w) * sp) / den;
-      T a = p.dt * al;
+      T f = ((p.dt * p.gn2) * sp) / den;
+      if (re(f) > 1.0) f = T(1.0);
+      T a = f * C.w;
       Pn = Pn - a;
       Mn = Mn - a;
     }

@@ -4,10 +4,12 @@ without a GPU).
     python -m paper_1410_0753_amd.build [--verbose]
 
 Flags: -O3, no FMA contraction (the FP64 path reproduces a written operation
-order bit for bit), packed FP32 instructions disabled.
+order bit for bit), packed FP32 instructions disabled.  The sources are
+compiled to objects in parallel and linked into one shared library.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -16,28 +18,43 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libclf.so")
+OBJ_DIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(CSRC, "clf_kernels.hip"), os.path.join(CSRC, "clf_adjoint.hip"),
            os.path.join(CSRC, "clf_runtime.cpp")]
 ARCH = os.environ.get("CLF_OFFLOAD_ARCH", "gfx950")
 
-FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          "-ffp-contract=off", "-fno-fast-math",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc"] + FLAGS + list(extra) + SOURCES + ["-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libclf.so")
+        raise RuntimeError("hipcc failed: %s" % " ".join(cmd[-3:]))
     if verbose and res.stderr:
         sys.stderr.write(res.stderr)
-    os.replace(tmp, LIB)
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    tag = "%d" % os.getpid()
+    objs = [os.path.join(OBJ_DIR, os.path.basename(s) + "." + tag + ".o") for s in SOURCES]
+    cmds = [["hipcc"] + FLAGS + list(extra) + ["-c", s, "-o", o] for s, o in zip(SOURCES, objs)]
+    try:
+        with concurrent.futures.ThreadPoolExecutor(len(cmds)) as ex:
+            list(ex.map(lambda c: _run(c, verbose), cmds))
+        tmp = LIB + ".tmp" + tag
+        _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp], verbose)
+        os.replace(tmp, LIB)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return LIB
 
 

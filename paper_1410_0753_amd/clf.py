@@ -23,11 +23,13 @@ CARTESIAN, SPHERICAL = 0, 1
 FP64, FP32 = 0, 1
 ORDER_XY, ORDER_ALTERNATE = 0, 1
 WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
+FRICTION_EXPLICIT, FRICTION_SEMI_IMPLICIT = 0, 1
+OPEN_W, OPEN_E, OPEN_S, OPEN_N = 1, 2, 4, 8
 (Q_MAX_CFL, Q_SSL_PASSES, Q_STEP, Q_MIN_F, Q_WORKSPACE, Q_GAUGE_RECORDS, Q_TILES, Q_SEGMENT,
  Q_BLOCKS, Q_GRAPH_REPLAYS, Q_WIDE) = range(1, 12)
 
 # Every symbol include/clf.h declares.
-EXPORTS = ["clf_default_params", "clf_workspace_bytes", "clf_init", "clf_set_initial",
+EXPORTS = ["clf_default_params", "clf_node_index", "clf_workspace_bytes", "clf_init", "clf_set_initial",
            "clf_set_raw_state", "clf_get_raw_state", "clf_set_boundary_forcing", "clf_set_gauges",
            "clf_add_enclosed_grid", "clf_step", "clf_sweep", "clf_get_state", "clf_get_depth",
            "clf_read_gauges", "clf_read_maxwave", "clf_read_boundary_series",
@@ -60,7 +62,8 @@ class Params(C.Structure):
                 ("max_enclosed", C.c_int32), ("max_enclosed_points", C.c_int32),
                 ("series_capacity", C.c_int32), ("forcing_capacity", C.c_int32),
                 ("segment", C.c_int32), ("autotune", C.c_int32),
-                ("graph_steps", C.c_int32), ("persistent_blocks", C.c_int32)]
+                ("graph_steps", C.c_int32), ("persistent_blocks", C.c_int32),
+                ("friction_form", C.c_int32), ("open_sides", C.c_int32)]
 
 
 _lock = threading.Lock()
@@ -82,6 +85,7 @@ def load(build_if_missing: bool = True):
         vp, i32, dbl = C.c_void_p, C.c_int, C.c_double
         sig = {
             "clf_default_params": (None, [C.POINTER(Params)]),
+            "clf_node_index": (i32, [i32, i32, i32, i32, C.POINTER(C.c_int64)]),
             "clf_workspace_bytes": (i32, [C.POINTER(Grid), C.POINTER(Params), C.POINTER(C.c_size_t)]),
             "clf_init": (i32, [C.POINTER(vp), C.POINTER(Grid), vp, dbl, C.POINTER(Params), vp, vp,
                                C.c_size_t]),
@@ -183,6 +187,7 @@ class Solver:
     def from_case(cls, case, **kw):
         kw.setdefault("h_min", case.h_min)
         kw.setdefault("manning_n2", getattr(case, "manning_n2", 0.0))
+        kw.setdefault("friction_form", getattr(case, "friction_form", 0))
         return cls(case.x, case.y, case.depth, case.dt, coord=case.coord, **kw)
 
     # -- errors --

@@ -154,16 +154,24 @@ __device__ void update_node(const Nd& L, const Nd& C, const Nd& R, double iL, do
     Pn = Pn + s3;
     Mn = Mn - s3;
   }
+  D3 fr = dc(0.0);
+  if (p.flags & G_FRICTION) {
+    D3 sp = dsqrt(C.w * C.w + C.t * C.t);
+    D3 den = C.H * dcbrt(C.H);
+    fr = ((p.dt * p.gn2) * sp) / den;
+    if (!(p.flags & G_FRIC_SEMI)) {
+      // -alpha dt on p and q (solver2), alpha at the old level, alpha dt =
+      // fr w with fr capped at 1 (friction does not reverse the flow)
+      const D3 a = (fr.v < 1.0 ? fr : dc(1.0)) * C.w;
+      Pn = Pn - a;
+      Mn = Mn - a;
+    }
+  }
   D3 wv = 0.5 * (Pn + Mn);
   D3 dd = Pn - Mn;
   if (dd.v < 0.0) dd = dc(0.0);
   D3 Hv = (dd * dd) * p.inv16g;
-  if (p.flags & G_FRICTION) {
-    D3 sp = dsqrt(C.w * C.w + C.t * C.t);
-    D3 den = C.H * dcbrt(C.H);
-    D3 fr = ((p.dt * p.gn2) * sp) / den;
-    wv = wv / (dc(1.0) + fr);
-  }
+  if ((p.flags & G_FRICTION) && (p.flags & G_FRIC_SEMI)) wv = wv / (dc(1.0) + fr);
   Ho = Hv; wo = wv; to = Tn;
 }
 
@@ -280,6 +288,21 @@ __device__ __forceinline__ Vjp3 vjp_local(const NodeIn& nl, const NodeIn& nc, co
     Pn = Pn + s3;
     Mn = Mn - s3;
   }
+  const bool fric = (p.flags & G_FRICTION) != 0;
+  const bool semi = fric && (p.flags & G_FRIC_SEMI) != 0;
+  double sp = 0.0, cb = 0.0, den = 1.0, fr = 0.0;
+  if (fric) {
+    sp = sqrt(Cw * Cw + Ct * Ct);
+    cb = cbrt(nc.H);
+    den = nc.H * cb;
+    fr = ((p.dt * p.gn2) * sp) / den;
+    if (!semi) {
+      // -alpha dt on p and q (solver2), alpha dt = fr w, fr capped at 1
+      const double fe = fr < 1.0 ? fr : 1.0;
+      Pn = Pn - fe * Cw;
+      Mn = Mn - fe * Cw;
+    }
+  }
   const double dd = Pn - Mn;
   const bool clipped = dd < 0.0;
 
@@ -288,15 +311,24 @@ __device__ __forceinline__ Vjp3 vjp_local(const NodeIn& nl, const NodeIn& nc, co
   double gLw = 0.0, gLt = 0.0, gLc = 0.0;
   double gRw = 0.0, gRt = 0.0, gRc = 0.0;
   double gwv = gW;
-  if (p.flags & G_FRICTION) {
+  double gfr = 0.0;
+  if (semi) {
     const double wv0 = 0.5 * (Pn + Mn);
-    const double sp = sqrt(Cw * Cw + Ct * Ct);
-    const double cb = cbrt(nc.H);
-    const double den = nc.H * cb;
-    const double fr = ((p.dt * p.gn2) * sp) / den;
     const double q = 1.0 + fr;
     gwv = gW / q;
-    const double gfr = -gW * (wv0 / q) / q;
+    gfr = -gW * (wv0 / q) / q;
+  }
+  const double gdd = clipped ? 0.0 : gH * (2.0 * dd * p.inv16g);
+  double gPn = 0.5 * gwv + gdd;
+  double gMn = 0.5 * gwv - gdd;
+  if (fric && !semi) {
+    // a = fe w subtracted from both: da = -(gPn + gMn); the cap fe = 1 has
+    // no derivative with respect to fr
+    const double ga = -(gPn + gMn);
+    gCw += ga * (fr < 1.0 ? fr : 1.0);
+    if (fr < 1.0) gfr += ga * Cw;
+  }
+  if (fric) {
     const double gsp = gfr * (p.dt * p.gn2) / den;
     const double gden = -gfr * fr / den;
     if (sp > 0.0) {
@@ -305,9 +337,6 @@ __device__ __forceinline__ Vjp3 vjp_local(const NodeIn& nl, const NodeIn& nc, co
     }
     gCH += gden * (cb + nc.H * (1.0 / (3.0 * cb * cb)));
   }
-  const double gdd = clipped ? 0.0 : gH * (2.0 * dd * p.inv16g);
-  double gPn = 0.5 * gwv + gdd;
-  double gMn = 0.5 * gwv - gdd;
   if (tanR != 0.0) {
     const double gs3 = gPn - gMn;
     gCc += gs3 * (p.dt * Cw * tanR);
@@ -736,11 +765,11 @@ __global__ __launch_bounds__(64) void adjoint_general_kernel(GridDesc g, SweepAr
 // A record is (h - d, u, v) on wet nodes, zeros on dry ones.  One thread per
 // gauge node: the first gauge on a node adds the records of every gauge on
 // that node, in gauge order (deterministic, no atomics).
-__global__ void inject_kernel(GridDesc g, const double* H, const int* gidx, int ng,
+__global__ void inject_kernel(GridDesc g, const double* H, const long long* gidx, int ng,
                               const double* rec_adj, double* lamH, double* lamU, double* lamV) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= ng) return;
-  const int k = gidx[q];
+  const long long k = gidx[q];
   for (int r = 0; r < q; ++r)
     if (gidx[r] == k) return;
   if (!(H[k] > g.hmin)) return;
@@ -798,7 +827,7 @@ hipError_t launch_adjoint_sweep(const GridDesc* gd_host, int axis, const double*
   return hipGetLastError();
 }
 
-hipError_t launch_inject(const GridDesc* gd_host, const double* H, const int* gidx, int ng,
+hipError_t launch_inject(const GridDesc* gd_host, const double* H, const long long* gidx, int ng,
                          const double* rec_adj, double* lamH, double* lamU, double* lamV,
                          hipStream_t s) {
   if (ng <= 0) return hipSuccess;

@@ -4,6 +4,9 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <vector>
+
+#include "clf.h"
 
 namespace clf {
 
@@ -13,6 +16,7 @@ enum : int {
   F_WET = 2,   // wet
   F_FIX = 4,   // forcing ring node: held, not updated by the sweeps
   F_FLD = 8,   // flooded in step (b) of this sweep
+  F_OPEN = 16, // outside the grid beyond an open (radiating) edge
 };
 
 // grid flags
@@ -28,6 +32,12 @@ enum : int {
   G_WIDE = 256,     // field arrays above 4 GiB: 64-bit addresses in the step kernel
   G_TINYH = 512,    // FP64 with h_min below 1e-200: wet depths may need the
                     // small-argument path of the square root
+  G_FRIC_SEMI = 1024,  // friction in the semi-implicit form (option) instead of -alpha dt
+  G_OPEN_W = 2048,     // open (radiating) edges
+  G_OPEN_E = 4096,
+  G_OPEN_S = 8192,
+  G_OPEN_N = 16384,
+  G_OPEN_ANY = G_OPEN_W | G_OPEN_E | G_OPEN_S | G_OPEN_N,
 };
 
 // kernel orders
@@ -73,7 +83,7 @@ struct SampleDesc {
   int gout;
   int npts;          // enclosed-grid boundary points (all grids, all sides)
   int bndout;
-  const int* gidx;   // [ngauge] node index iy*nx + ix
+  const long long* gidx;  // [ngauge] node index iy*nx + ix
   double* grec;      // [cap][ngauge][3]
   int gcap;
   const long long* sidx;  // [npts][4] corner node indices
@@ -130,6 +140,23 @@ hipError_t launch_forcing(int fp32, const GridDesc* gd_dev, const ForceDesc* fd_
 hipError_t launch_deform_depth(int fp32, const GridDesc* gd_host, const double* eta, long long N,
                                hipStream_t s);
 
+// Host helpers of the runtime (clf_runtime.cpp), shared with the
+// no-allocation entry point (clf_static.hip).
+struct GridMetrics {
+  // inverse spacings: x [nx+1], [nx]; row factor [ny]; y [ny+1], [ny]; tan(lat)/R [ny]
+  std::vector<double> xib, xisb, xfac, yib, yisb, tanR;
+};
+void build_metrics(const clf_grid& g, const clf_params& p, GridMetrics& m);
+int grid_flags(const clf_grid& g, const clf_params& p);
+void set_step_constants(GridDesc& gd, double dt, const clf_params& p);
+// XCD-ordered tile list of one grid for a segment length; *nblocks receives
+// the workgroup count of a launch that covers it
+std::vector<Tile> grid_tiles(int nx, int ny, int seg, int* nblocks);
+int grid_default_segment(int nx, int ny, int fp32, int gflags);
+int step_order_for(int nx, int ny);
+int validate_args(const clf_grid* g, const clf_params* p);
+void set_init_error(const char* msg);
+
 // Flags used by the adjoint sweep (bytes; zero them once before the first
 // sweep, every sweep leaves them zero).
 int adjoint_flag_count(int nx, int ny);
@@ -137,7 +164,7 @@ hipError_t launch_adjoint_sweep(const GridDesc* gd_host, int axis, const double*
                                 const double* preU, const double* preV, const double* lamH,
                                 const double* lamU, const double* lamV, double* outH,
                                 double* outU, double* outV, unsigned char* flags, hipStream_t s);
-hipError_t launch_inject(const GridDesc* gd_host, const double* H, const int* gidx, int ng,
+hipError_t launch_inject(const GridDesc* gd_host, const double* H, const long long* gidx, int ng,
                          const double* rec_adj, double* lamH, double* lamU, double* lamV,
                          hipStream_t s);
 hipError_t launch_initial_adjoint(const GridDesc* gd_host, const double* H0, const double* lamH,

@@ -341,16 +341,34 @@ struct P64 {
 
   // (d) with every neighbour evaluated in place (needed by solver1, whose
   // centred term spans both neighbours)
+  // Ghost beyond an open (radiating) edge: it carries the node's outgoing
+  // Riemann invariant and the still-water incoming one (p0 = 2 sqrt(g d) from
+  // the left, q0 = -2 sqrt(g d) from the right); w = (p + q)/2 and
+  // c = max((p - q)/4, 0).
+  static __device__ __forceinline__ void open_ghost(double w, double c, double D, bool right,
+                                                    double& wg, double& cg) {
+    const double c0 = sqrt(kG * (D > 0.0 ? D : 0.0));
+    const double pp = right ? w + 2.0 * c : 2.0 * c0;
+    const double qq = right ? -2.0 * c0 : w - 2.0 * c;
+    wg = 0.5 * (pp + qq);
+    const double cc = 0.25 * (pp - qq);
+    cg = cc < 0.0 ? 0.0 : cc;
+  }
+
   static __device__ __forceinline__ C stage_cd(const Bx& l, const B& c, const Bx& r, double iL,
                                                double iR, double iS, double tanR, const Par& p) {
     const bool lreal = (l.f & (F_EX | F_WET)) == (F_EX | F_WET);
     const bool rreal = (r.f & (F_EX | F_WET)) == (F_EX | F_WET);
     const double Cw = c.w, Ct = c.t, CD = c.D, Cc = c.c;
     // mirror ghost (h_k, -w_k, t_k, d_k) where the neighbour is dry or missing
-    const double Lw = lreal ? l.w : -Cw, Lt = lreal ? l.t : Ct, LD = lreal ? l.D : CD,
-                 Lc = lreal ? l.c : Cc;
-    const double Rw = rreal ? r.w : -Cw, Rt = rreal ? r.t : Ct, RD = rreal ? r.D : CD,
-                 Rc = rreal ? r.c : Cc;
+    double Lw = lreal ? l.w : -Cw, Lc = lreal ? l.c : Cc;
+    double Rw = rreal ? r.w : -Cw, Rc = rreal ? r.c : Cc;
+    const double Lt = lreal ? l.t : Ct, LD = lreal ? l.D : CD;
+    const double Rt = rreal ? r.t : Ct, RD = rreal ? r.D : CD;
+    if (p.flags & G_OPEN_ANY) {
+      if (!lreal && (l.f & F_OPEN)) open_ghost(Cw, Cc, CD, false, Lw, Lc);
+      if (!rreal && (r.f & F_OPEN)) open_ghost(Cw, Cc, CD, true, Rw, Rc);
+    }
     const Fx QL = flux(Lw, Lc, LD, Lt, Cw, Cc, CD, Ct, iL);
     const Fx QR = flux(Cw, Cc, CD, Ct, Rw, Rc, RD, Rt, iR);
     double QPc = 0.0, QMc = 0.0, QTc = 0.0;
@@ -379,24 +397,34 @@ struct P64 {
       Pn = Pn + s3;
       Mn = Mn - s3;
     }
-    double ws = Pn + Mn;
-    double wv = 0.5 * ws;
-    double dd = Pn - Mn;
-    dd = (dd < 0.0) ? 0.0 : dd;
-    double Hv = (dd * dd) * p.inv16g;
+    // Manning friction: fr = dt g n^2 |U| / h^(4/3) with h^(-1/3) from a
+    // single-precision seed (hardware log2 / exp2) and two Newton steps
+    // r <- r (4 - h r^3) / 3: no libm cbrt and no division; agrees with the
+    // direct form to rounding
+    double fr = 0.0;
     if (p.flags & G_FRICTION) {
-      // k sp / h^(4/3) with h^(-1/3) from a single-precision seed (hardware
-      // log2 / exp2) and two Newton steps r <- r (4 - h r^3) / 3: no libm
-      // cbrt and no division; agrees with the direct form to rounding
       double sp = sqrt(Cw * Cw + Ct * Ct);
       const double h = c.H;
       double r = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)h) * (-1.0f / 3.0f));
       r = r * ((4.0 - h * ((r * r) * r)) * (1.0 / 3.0));
       r = r * ((4.0 - h * ((r * r) * r)) * (1.0 / 3.0));
       const double r2 = r * r;
-      double fr = ((p.dt * p.gn2) * sp) * (r2 * r2);
-      wv = wv / (1.0 + fr);
+      fr = ((p.dt * p.gn2) * sp) * (r2 * r2);
+      if (!(p.flags & G_FRIC_SEMI)) {
+        // the -alpha dt term of solver2 / solver1 on p and q (old level),
+        // alpha dt = fr w with fr capped at 1: friction does not reverse the flow
+        const double a = (fr < 1.0 ? fr : 1.0) * Cw;
+        Pn = Pn - a;
+        Mn = Mn - a;
+      }
     }
+    double ws = Pn + Mn;
+    double wv = 0.5 * ws;
+    double dd = Pn - Mn;
+    dd = (dd < 0.0) ? 0.0 : dd;
+    double Hv = (dd * dd) * p.inv16g;
+    // option: semi-implicit friction on the normal velocity
+    if ((p.flags & G_FRICTION) && (p.flags & G_FRIC_SEMI)) wv = wv / (1.0 + fr);
     const bool wet = (c.f & F_WET) != 0;
     C o;
     o.H = wet ? Hv : 0.0;
@@ -599,16 +627,34 @@ struct P32 {
     return finish(c, FL.P, FR.P, FL.M, FR.M, FL.T, FR.T, 0.f, 0.f, 0.f, iS, tanR, p);
   }
 
+  // Ghost beyond an open edge (as in the FP64 stages).  Its surface differs
+  // from the node's by the height difference (c_g^2 - c^2)/g, formed as a
+  // product of differences so that it is exactly zero at rest.
+  static __device__ __forceinline__ void open_ghost(float w, float c, float e, float D, bool right,
+                                                    float& wg, float& cg, float& eg) {
+    const float c0 = __builtin_amdgcn_sqrtf(kGf * (D > 0.f ? D : 0.f));
+    const float pp = right ? w + 2.f * c : 2.f * c0;
+    const float qq = right ? -2.f * c0 : w - 2.f * c;
+    wg = 0.5f * (pp + qq);
+    const float cc = 0.25f * (pp - qq);
+    cg = cc < 0.f ? 0.f : cc;
+    eg = e + ((cg - c) * (cg + c)) * (1.f / kGf);
+  }
+
   static __device__ __forceinline__ C stage_cd(const Bx& l, const B& c, const Bx& r, float iL,
                                                float iR, float iS, float tanR, const Par& p) {
     const bool lreal = (l.f & (F_EX | F_WET)) == (F_EX | F_WET);
     const bool rreal = (r.f & (F_EX | F_WET)) == (F_EX | F_WET);
     const float Cw = c.w, Ct = c.t, CD = c.D, Cc = c.c, Ce = c.H;
     // mirror ghost where the neighbour is dry or missing
-    const float Lw = lreal ? l.w : -Cw, Lt = lreal ? l.t : Ct, LD = lreal ? l.D : CD,
-                Lc = lreal ? l.c : Cc, Le = lreal ? l.H : Ce;
-    const float Rw = rreal ? r.w : -Cw, Rt = rreal ? r.t : Ct, RD = rreal ? r.D : CD,
-                Rc = rreal ? r.c : Cc, Re = rreal ? r.H : Ce;
+    float Lw = lreal ? l.w : -Cw, Lc = lreal ? l.c : Cc, Le = lreal ? l.H : Ce;
+    float Rw = rreal ? r.w : -Cw, Rc = rreal ? r.c : Cc, Re = rreal ? r.H : Ce;
+    const float Lt = lreal ? l.t : Ct, LD = lreal ? l.D : CD;
+    const float Rt = rreal ? r.t : Ct, RD = rreal ? r.D : CD;
+    if (p.flags & G_OPEN_ANY) {
+      if (!lreal && (l.f & F_OPEN)) open_ghost(Cw, Cc, Ce, CD, false, Lw, Lc, Le);
+      if (!rreal && (r.f & F_OPEN)) open_ghost(Cw, Cc, Ce, CD, true, Rw, Rc, Re);
+    }
     const Fx QL = flux(Lw, Lc, Le, LD, Lt, Cw, Cc, Ce, CD, Ct, iL);
     const Fx QR = flux(Cw, Cc, Ce, CD, Ct, Rw, Rc, Re, RD, Rt, iR);
     float QPc = 0.f, QMc = 0.f, QTc = 0.f;
@@ -639,11 +685,16 @@ struct P32 {
     const float hv = drained ? 0.f : c.h + dh;
     const float ev = drained ? -CD : Ce + dh;
     if (p.flags & G_FRICTION) {
-      // k sp h^(-4/3) through the hardware log2 / exp2 and reciprocal
+      // fr = dt g n^2 |U| h^(-4/3) through the hardware log2 / exp2.  The
+      // -alpha dt term on p and q moves u by -alpha dt and leaves p - q
+      // (hence h) unchanged, so it is applied to u directly.
       const float sp = __builtin_amdgcn_sqrtf(Cw * Cw + Ct * Ct);
       const float hm43 = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(c.h) * (-4.0f / 3.0f));
       const float fr = ((p.dt * p.gn2) * sp) * hm43;
-      wv = wv * __builtin_amdgcn_rcpf(1.f + fr);
+      if (p.flags & G_FRIC_SEMI)
+        wv = wv * __builtin_amdgcn_rcpf(1.f + fr);
+      else
+        wv = wv - (fr < 1.f ? fr : 1.f) * Cw;
     }
     const bool wet = (c.f & F_WET) != 0;
     C o;
@@ -711,6 +762,14 @@ __device__ __forceinline__ int ring_flag(int gflags, int xc, int r, int nx, int 
              : 0;
 }
 
+// a node outside the grid beyond an open edge (its ghost is the open one)
+__device__ __forceinline__ int open_flag(int gflags, int xc, int r, int nx, int ny) {
+  return ((gflags & G_OPEN_W) && xc < 0) || ((gflags & G_OPEN_E) && xc >= nx) ||
+                 ((gflags & G_OPEN_S) && r < 0) || ((gflags & G_OPEN_N) && r >= ny)
+             ? F_OPEN
+             : 0;
+}
+
 // a neighbour that takes part in (d) with its own values: inside the grid
 // and wet after (b); any other neighbour is replaced by the mirror ghost
 __device__ __forceinline__ bool is_real(int f) { return (f & (F_EX | F_WET)) == (F_EX | F_WET); }
@@ -740,7 +799,7 @@ __device__ __forceinline__ typename P::C xsweep_row(typename P::A a, typename P:
   typename P::Bx bx = P::bx(b);
   typename P::Bx br = from_next(bx);
   C c;
-  if (par.flags & G_SOLVER1) {
+  if (par.flags & (G_SOLVER1 | G_OPEN_ANY)) {
     typename P::Bx bl = from_prev(bx);
     c = P::stage_cd(bl, b, br, iL, iR, iS, (typename P::R)0, par);
   } else {
@@ -878,7 +937,7 @@ __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_i
 // FL: the grid flags this instantiation honours (others are compiled out).
 constexpr int FL_FAST = G_SPHSRC;
 // runup workloads: the common case plus bottom friction
-constexpr int FL_FRIC = G_SPHSRC | G_FRICTION;
+constexpr int FL_FRIC = G_SPHSRC | G_FRICTION | G_FRIC_SEMI;
 // grids driven by boundary forcing (a forcing ring), without and with
 // friction. These sets also take wall mode, which changes only step (b) in
 // the ballot-guarded flooding branch (in the common set the extra code
@@ -886,7 +945,7 @@ constexpr int FL_FRIC = G_SPHSRC | G_FRICTION;
 constexpr int FL_RING = FL_FAST | G_WALLMODE | G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N;
 constexpr int FL_RING_FRIC = FL_RING | G_FRICTION;
 constexpr int FL_ALL = G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N | G_WALLMODE | G_SOLVER1 |
-                       G_SPHSRC | G_FRICTION | G_TINYH;
+                       G_SPHSRC | G_FRICTION | G_FRIC_SEMI | G_TINYH | G_OPEN_ANY;
 // grids whose field arrays exceed 4 GiB: the same three flag sets with
 // 64-bit addresses
 constexpr int FL_FAST_WIDE = FL_FAST | G_WIDE;
@@ -961,6 +1020,7 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
     cx.par.flags = g.flags & FL;
     const R* xfac = (const R*)g.xfac;
     constexpr bool kRing = (FL & (G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N)) != 0;
+    constexpr bool kOpen = (FL & G_OPEN_ANY) != 0;
 
     const int nx = cx.nx, ny = cx.ny;
     const int xc = tl.x0 - HALO + lane;
@@ -997,6 +1057,7 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
       a.t = ld(cx.V, b);
       a.f = (col_in && r >= 0 && r < ny) ? F_EX : 0;
       if (kRing) a.f |= ring_flag(cx.gflags, xc, r, nx, ny);
+      if (kOpen) a.f |= open_flag(cx.gflags, xc, r, nx, ny);
     };
     // maxwave values of an output row, read one march row ahead of use
     struct MW { R e, s2; };
@@ -1081,7 +1142,7 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
             if (writes && ro < ny) {
               A ax;
               ax.H = oy.H; ax.w = oy.t; ax.t = oy.w;
-              ax.f = ob.f & (F_EX | F_FIX);
+              ax.f = ob.f & (F_EX | F_FIX | F_OPEN);
               ax.D = ob.D;
               R f = cload(xfac + ro);
               C o = xsweep_row<P>(ax, f * xiL, f * xiR, f * xiS, cx.par);
@@ -1265,7 +1326,7 @@ __global__ void sample_kernel(const GridDesc* grids, const SampleDesc* sd, long 
   if (s.ngauge > 0 && n % s.gout == 0 && n >= s.g_first && i < s.ngauge) {
     const long long slot = (n - s.g_first) / s.gout;
     if (slot < s.gcap) {
-      const int k = s.gidx[i];
+      const long long k = s.gidx[i];
       R e;
       const bool w = node_wet<R>(g, H[k], D[k], e);
       double* o = s.grec + ((size_t)slot * s.ngauge + i) * 3;

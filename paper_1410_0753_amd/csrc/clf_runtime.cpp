@@ -113,7 +113,7 @@ Layout plan(int nx, int ny, const clf_params& p) {
   L.yib = take(es * (ny + 1));
   L.yisb = take(es * ny);
   L.tanR = take(es * ny);
-  L.gidx = take(sizeof(int) * std::max(p.max_gauges, 1));
+  L.gidx = take(sizeof(long long) * std::max(p.max_gauges, 1));
   L.grec = take(sizeof(double) * 3 * (size_t)std::max(p.max_gauges, 1) *
                 std::max(p.gauge_capacity, 1));
   const size_t mp = std::max(p.max_enclosed_points, 1);
@@ -536,6 +536,13 @@ long long records_between(long long first, int every, long long lo, long long hi
 
 extern "C" {
 
+int clf_node_index(int nx, int ny, int ix, int iy, int64_t* index) {
+  if (!index || nx < 1 || ny < 1 || ix < 0 || ix >= nx || iy < 0 || iy >= ny) return CLF_EINVAL;
+  // 64-bit arithmetic: grids hold up to 2^32 - 1 nodes
+  *index = (int64_t)iy * (int64_t)nx + (int64_t)ix;
+  return CLF_OK;
+}
+
 void clf_default_params(clf_params* p) {
   std::memset(p, 0, sizeof *p);
   p->precision = CLF_FP64;
@@ -576,6 +583,79 @@ static bool wide_offsets(int nx, int ny, int fp32) {
   return e && e[0] == '1';
 }
 
+static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c);
+
+}  // extern "C"
+
+namespace clf {
+
+void build_metrics(const clf_grid& g, const clf_params& p, GridMetrics& m) {
+  const std::vector<double> x(g.x, g.x + g.nx), y(g.y, g.y + g.ny);
+  m.xfac.assign(g.ny, 1.0);
+  m.tanR.assign(g.ny, 0.0);
+  const double deg = kPiD / 180.0;
+  if (g.coord == CLF_SPHERICAL) {
+    // x spacing in degrees with a per-row factor 1/(R cos(lat) pi/180); y in metres
+    const double Rd = p.earth_radius * deg;
+    line_inverse_spacings(x, 1.0, m.xib, m.xisb);
+    for (int j = 0; j < g.ny; ++j) m.xfac[j] = 1.0 / (Rd * std::cos(y[j] * deg));
+    line_inverse_spacings(y, Rd, m.yib, m.yisb);
+    if (p.spherical_metric)
+      for (int j = 0; j < g.ny; ++j) m.tanR[j] = std::tan(y[j] * deg) / p.earth_radius;
+  } else {
+    line_inverse_spacings(x, 1.0, m.xib, m.xisb);
+    line_inverse_spacings(y, 1.0, m.yib, m.yisb);
+  }
+}
+
+int grid_flags(const clf_grid& g, const clf_params& p) {
+  int flags = 0;
+  const int fp32 = p.precision == CLF_FP32;
+  if (g.coord == CLF_SPHERICAL && p.spherical_metric) flags |= G_SPHSRC;
+  if (p.itopo == 0) flags |= G_WALLMODE;
+  if (p.solver == 1) flags |= G_SOLVER1;
+  if (p.manning_n2 > 0.0) flags |= G_FRICTION;
+  if (p.manning_n2 > 0.0 && p.friction_form == 1) flags |= G_FRIC_SEMI;
+  // open edges of a 1-D grid: only the ends along its one dimension matter
+  if (p.open_sides & 1) flags |= G_OPEN_W;
+  if (p.open_sides & 2) flags |= G_OPEN_E;
+  if (p.open_sides & 4) flags |= G_OPEN_S;
+  if (p.open_sides & 8) flags |= G_OPEN_N;
+  if (wide_offsets(g.nx, g.ny, fp32)) flags |= G_WIDE;
+  if (!fp32 && p.h_min < 1e-200) flags |= G_TINYH;
+  return flags;
+}
+
+void set_step_constants(GridDesc& gd, double dt, const clf_params& p) {
+  gd.dt = dt;
+  gd.hdt = 0.5 * dt;
+  gd.dt2 = dt * dt;
+  gd.hmin = p.h_min;
+  gd.gn2 = kGrav * p.manning_n2;
+  gd.inv16g = 1.0 / (16.0 * kGrav);
+  gd.dwall = p.dwall;
+}
+
+std::vector<Tile> grid_tiles(int nx, int ny, int seg, int* nblocks) {
+  std::vector<Tile> nat;
+  natural_tiles(0, nx, ny, seg, nat);
+  return xcd_order(nat, nblocks);
+}
+
+int grid_default_segment(int nx, int ny, int fp32, int gflags) {
+  return default_segment(nx, ny, resident_per_xcd(fp32, step_order_of(nx, ny), gflags));
+}
+
+int step_order_for(int nx, int ny) { return step_order_of(nx, ny); }
+
+int validate_args(const clf_grid* g, const clf_params* p) { return validate(g, p, nullptr); }
+
+void set_init_error(const char* msg) { g_init_error = msg; }
+
+}  // namespace clf
+
+extern "C" {
+
 static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c) {
   if (!g || !p) return fail(c, CLF_EINVAL, "null grid or params");
   if (g->nx < 1 || g->ny < 1) return fail(c, CLF_EINVAL, "nx, ny must be >= 1");
@@ -604,6 +684,10 @@ static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c) {
   if (!(p->h_min > 0.0)) return fail(c, CLF_EINVAL, "h_min must be > 0");
   if (p->manning_n2 < 0.0) return fail(c, CLF_EINVAL, "manning_n2 must be >= 0");
   if (p->solver != 1 && p->solver != 2) return fail(c, CLF_EINVAL, "solver must be 1 or 2");
+  if (p->friction_form != 0 && p->friction_form != 1)
+    return fail(c, CLF_EINVAL, "friction_form must be 0 (explicit) or 1 (semi-implicit)");
+  if (p->open_sides < 0 || p->open_sides > 15)
+    return fail(c, CLF_EINVAL, "open_sides must be a bit mask of the four sides (0..15)");
   if (p->sweep_order != CLF_ORDER_XY && p->sweep_order != CLF_ORDER_ALTERNATE)
     return fail(c, CLF_EINVAL, "bad sweep order");
   if (p->maxout < 1 || p->gout < 1 || p->bndout < 1)
@@ -677,22 +761,10 @@ static int ctx_create(clf_ctx** out, const clf_grid* g, const double* depth, dou
   }
 
   // metrics
-  std::vector<double> xib, xisb, yib, yisb, xfac(c->ny, 1.0), tanR(c->ny, 0.0);
-  const double deg = kPiD / 180.0;
-  int flags = 0;
-  if (c->coord == CLF_SPHERICAL) {
-    const double Rd = p->earth_radius * deg;
-    line_inverse_spacings(c->x, 1.0, xib, xisb);
-    for (int j = 0; j < c->ny; ++j) xfac[j] = 1.0 / (Rd * std::cos(c->y[j] * deg));
-    line_inverse_spacings(c->y, Rd, yib, yisb);
-    if (p->spherical_metric) {
-      for (int j = 0; j < c->ny; ++j) tanR[j] = std::tan(c->y[j] * deg) / p->earth_radius;
-      flags |= G_SPHSRC;
-    }
-  } else {
-    line_inverse_spacings(c->x, 1.0, xib, xisb);
-    line_inverse_spacings(c->y, 1.0, yib, yisb);
-  }
+  GridMetrics M;
+  build_metrics(*g, *p, M);
+  const std::vector<double>&xib = M.xib, &xisb = M.xisb, &yib = M.yib, &yisb = M.yisb,
+                            &xfac = M.xfac, &tanR = M.tanR;
 
   // still-water Courant number over wet nodes, and min f_j (eq:f)
   double cmax = 0.0, fmin = 1e300;
@@ -729,12 +801,7 @@ static int ctx_create(clf_ctx** out, const clf_grid* g, const double* depth, dou
   GridDesc& gd = c->gd;
   gd.nx = c->nx;
   gd.ny = c->ny;
-  if (p->itopo == 0) flags |= G_WALLMODE;
-  if (p->solver == 1) flags |= G_SOLVER1;
-  if (p->manning_n2 > 0.0) flags |= G_FRICTION;
-  if (wide_offsets(c->nx, c->ny, c->fp32)) flags |= G_WIDE;
-  if (!c->fp32 && p->h_min < 1e-200) flags |= G_TINYH;
-  gd.flags = flags;
+  gd.flags = grid_flags(*g, *p);
   gd.maxout = p->maxout;
   gd.H[0] = b + L.f[0]; gd.H[1] = b + L.f[1];
   gd.U[0] = b + L.f[2]; gd.U[1] = b + L.f[3];
@@ -748,13 +815,7 @@ static int ctx_create(clf_ctx** out, const clf_grid* g, const double* depth, dou
   gd.yib = b + L.yib;
   gd.yisb = b + L.yisb;
   gd.tanR = b + L.tanR;
-  gd.dt = dt;
-  gd.hdt = 0.5 * dt;
-  gd.dt2 = dt * dt;
-  gd.hmin = p->h_min;
-  gd.gn2 = kGrav * p->manning_n2;
-  gd.inv16g = 1.0 / (16.0 * kGrav);
-  gd.dwall = p->dwall;
+  set_step_constants(gd, dt, *p);
 
   hipStream_t s = c->stream;
   hipError_t e = hipSuccess;
@@ -777,7 +838,7 @@ static int ctx_create(clf_ctx** out, const clf_grid* g, const double* depth, dou
   c->sd = SampleDesc{};
   c->sd.gout = p->gout;
   c->sd.bndout = p->bndout;
-  c->sd.gidx = (const int*)(b + L.gidx);
+  c->sd.gidx = (const long long*)(b + L.gidx);
   c->sd.grec = (double*)(b + L.grec);
   c->sd.gcap = p->gauge_capacity;
   c->sd.sidx = (const long long*)(b + L.sidx);
@@ -899,14 +960,16 @@ int clf_set_gauges(clf_ctx* c, int n, const int32_t* ix, const int32_t* iy) {
   if (n < 0 || n > c->p.max_gauges)
     return fail(c, CLF_ENOSPACE, "%d gauges exceed max_gauges %d", n, c->p.max_gauges);
   if (n > 0 && (!ix || !iy)) return fail(c, CLF_EINVAL, "null gauge index");
-  std::vector<int> idx(n);
+  std::vector<long long> idx(n);
   for (int g = 0; g < n; ++g) {
     if (ix[g] < 0 || ix[g] >= c->nx || iy[g] < 0 || iy[g] >= c->ny)
       return fail(c, CLF_EINVAL, "gauge %d outside the grid", g);
-    idx[g] = iy[g] * c->nx + ix[g];
+    int64_t k = 0;
+    clf_node_index(c->nx, c->ny, ix[g], iy[g], &k);
+    idx[g] = (long long)k;
   }
   if (n > 0)
-    HIPCHK(c, hipMemcpyAsync((void*)c->sd.gidx, idx.data(), sizeof(int) * n,
+    HIPCHK(c, hipMemcpyAsync((void*)c->sd.gidx, idx.data(), sizeof(long long) * n,
                              hipMemcpyHostToDevice, c->stream));
   c->ngauge = n;
   // records restart at the current level (or at 0 before the first step)
@@ -1319,6 +1382,8 @@ int clf_adjoint_forward(clf_ctx* c, int nsteps, int ckpt_every, void* ws, size_t
   if (c->fp32) return fail(c, CLF_EINVAL, "the adjoint needs an FP64 context");
   if (c->p.sweep_order != CLF_ORDER_XY) return fail(c, CLF_EINVAL, "the adjoint needs the x-y order");
   if (c->forcing) return fail(c, CLF_EINVAL, "the adjoint does not support boundary forcing");
+  if (c->gd.flags & G_OPEN_ANY)
+    return fail(c, CLF_EINVAL, "the adjoint does not support open edges");
   if (c->n != 0 || c->rec0) return fail(c, CLF_ESTATE, "call clf_set_initial before the forward run");
   if (nsteps < 1 || ckpt_every < 0 || !ws) return fail(c, CLF_EINVAL, "bad adjoint arguments");
   const int K = adj_K(nsteps, ckpt_every);

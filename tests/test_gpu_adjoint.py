@@ -86,11 +86,13 @@ def test_adjoint_all_components_vs_complex_step(clf, oracle_mod, land):
         assert abs(ad - dL) <= 1e-9 * max(abs(dL), 1e-30) + 1e-14
 
 
-@pytest.mark.parametrize("variant", ["spherical", "solver1", "friction"])
+@pytest.mark.parametrize("variant", ["spherical", "solver1", "friction", "friction-semi"])
 def test_adjoint_variants_vs_complex_step(clf, oracle_mod, variant):
     # the reverse-mode interior path and the shoreline path under the
     # spherical continuity source (y-sweep), the solver1 stencil and friction
-    kw = {"solver1": dict(solver=1), "friction": dict(manning_n2=0.0009)}.get(variant, {})
+    # (the explicit -alpha dt form and the semi-implicit option)
+    kw = {"solver1": dict(solver=1), "friction": dict(manning_n2=0.0009),
+          "friction-semi": dict(manning_n2=0.0009, friction_form=1)}.get(variant, {})
     coord = synth.SPHERICAL if variant == "spherical" else synth.CARTESIAN
     c = synth.random_small(60, 66, 48, land=True, amp=0.3, coord=coord)
     nsteps = 30

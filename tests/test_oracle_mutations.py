@@ -37,12 +37,15 @@ MUTATIONS = [
     ("semi-implicit friction in place of the explicit -alpha dt",
      "if (p.n2 > 0.0 && p.fric_form == 0) {", "if (p.n2 > 0.0 && p.fric_form == 7) {",
      ["test_friction_explicit_one_step"]),
+    ("explicit friction without the no-reversal cap",
+     "if (re(f) > 1.0) f = T(1.0);", "",
+     ["test_friction_explicit_does_not_reverse_the_flow"]),
     ("friction on p only",
      "      Pn = Pn - a;\n      Mn = Mn - a;", "      Pn = Pn - a;",
      ["test_friction_explicit_one_step"]),
     ("friction speed without the tangential velocity",
-     "T sp = sqrt_t(C.w * C.w + C.t * C.t);\n      T den = C.H * cbrt_t(C.H);\n      T al",
-     "T sp = sqrt_t(C.w * C.w);\n      T den = C.H * cbrt_t(C.H);\n      T al",
+     "T sp = sqrt_t(C.w * C.w + C.t * C.t);\n      T den = C.H * cbrt_t(C.H);\n      T f =",
+     "T sp = sqrt_t(C.w * C.w);\n      T den = C.H * cbrt_t(C.H);\n      T f =",
      ["test_friction_explicit_one_step"]),
     ("open edge: incoming invariant taken from the node",
      "    pp = w + 2.0 * c;\n    qq = T(-2.0 * c0);", "    pp = w + 2.0 * c;\n    qq = w - 2.0 * c;",

@@ -466,6 +466,21 @@ def test_friction_explicit_one_step(oracle_mod):
     assert abs((0.8 - u1) - dt * k * 0.64) > 1e-6 * dt * k * 0.64
 
 
+def test_friction_explicit_does_not_reverse_the_flow(oracle_mod):
+    # a fast current in a thin layer: dt g n^2 |U| / h^(4/3) = 3.8 > 1, so the
+    # uncapped explicit term would reverse u to -2.8 u0 and grow; friction
+    # brings the flow to rest in one step instead (to the rounding of p and q)
+    h, n2, u0, dt = 0.2, 0.0009, 5.0, 10.0
+    f = dt * G * n2 * u0 / h ** (4.0 / 3.0)
+    assert f > 2.0
+    o = _uniform_current(oracle_mod, h, n2, u0, 0.0, dt)
+    o.step(1)
+    c0 = math.sqrt(G * h)
+    assert abs(o.raw_state()[1][20, 20]) <= 1e-14 * c0
+    o.step(20)
+    assert np.abs(o.raw_state()[1]).max() <= u0
+
+
 def test_friction_explicit_converges_to_decay_law(oracle_mod):
     # explicit in time: first-order convergence to 1/u = 1/u0 + k t
     h, n2, u0, T = 5.0, 0.0009, 0.5, 200.0
