@@ -318,6 +318,52 @@ int clf_ensemble_query(clf_ens* e, int what, double* value);
 const char* clf_ensemble_last_error(const clf_ens* e);
 int clf_ensemble_destroy(clf_ens* e);
 
+/* ------------------------------------------------------------------------
+ * One grid split into y-bands (row ranges) on one device: the per-GPU part
+ * of sharding a large grid over GPUs (the paper's splitting into independent
+ * row and column problems, section Numerics, eq2A/eq2B).  The x-sweep is
+ * row-local, and the y-sweep of a row needs the post-x state of HALO = 3
+ * rows on each side (steps (a)-(e) reach 3 nodes), so each band holds its
+ * own rows plus 3 halo rows beyond each inner edge.  A step is one launch of
+ * the step kernel over all bands' tiles, then one exchange: the 3 rows of
+ * (h, u, v) beyond each inner edge take the post-step values of the band
+ * that owns them (on several GPUs this is the point-to-point exchange with
+ * each neighbour).  Results are bit for bit those of a clf_init context on
+ * the whole grid.  Depth preprocessing and the Courant check run once, on
+ * the whole grid.  Bands use the x-y order; gauges, enclosed grids and
+ * forcing are not available on them (maxwave is).  Every band needs at
+ * least 3 rows.
+ * ------------------------------------------------------------------------ */
+typedef struct clf_bands clf_bands;
+
+/* Workspace for grid g split into nbands bands (caller-owned, device). */
+int clf_bands_workspace_bytes(const clf_grid* g, const clf_params* p, int nbands, size_t* bytes);
+
+/* As clf_init, for the whole grid (depth: host [ny][nx]); rows are dealt to
+ * the bands as evenly as possible, lower rows first. */
+int clf_bands_init(clf_bands** out, const clf_grid* g, const double* depth, double dt,
+                   const clf_params* p, int nbands, void* stream, void* ws, size_t ws_bytes);
+
+/* As clf_set_initial, with whole-grid device arrays [ny][nx]. */
+int clf_bands_set_initial(clf_bands* b, const double* eta, const double* u, const double* v,
+                          int deform_bottom);
+
+/* Advance nsteps steps (step launch + halo exchange each).  Asynchronous. */
+int clf_bands_step(clf_bands* b, int nsteps);
+
+/* As clf_get_state and clf_read_maxwave, into whole-grid device arrays
+ * (each band writes its own rows).  Synchronise the stream. */
+int clf_bands_get_state(clf_bands* b, double* eta, double* u, double* v, uint8_t* wet);
+int clf_bands_read_maxwave(clf_bands* b, double* eta_max, double* speed_max);
+
+int clf_bands_sync(clf_bands* b);
+/* CLF_Q_MAX_CFL, CLF_Q_MIN_F, CLF_Q_SSL_PASSES of the whole grid; CLF_Q_STEP,
+ * CLF_Q_TILES, CLF_Q_SEGMENT, CLF_Q_BLOCKS, CLF_Q_WIDE, CLF_Q_WORKSPACE of the
+ * launch over all bands. */
+int clf_bands_query(clf_bands* b, int what, double* value);
+const char* clf_bands_last_error(const clf_bands* b);
+int clf_bands_destroy(clf_bands* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,7 +38,10 @@ EXPORTS = ["clf_default_params", "clf_node_index", "clf_workspace_bytes", "clf_i
            "clf_ensemble_step", "clf_ensemble_get_state", "clf_ensemble_read_maxwave",
            "clf_ensemble_sync", "clf_ensemble_query", "clf_ensemble_last_error",
            "clf_ensemble_destroy", "clf_adjoint_workspace_bytes", "clf_adjoint_forward",
-           "clf_adjoint_backward"]
+           "clf_adjoint_backward", "clf_bands_workspace_bytes",
+           "clf_bands_init", "clf_bands_set_initial", "clf_bands_step", "clf_bands_get_state",
+           "clf_bands_read_maxwave", "clf_bands_sync", "clf_bands_query",
+           "clf_bands_last_error", "clf_bands_destroy"]
 
 
 class ClfError(RuntimeError):
@@ -121,6 +124,18 @@ def load(build_if_missing: bool = True):
             "clf_adjoint_workspace_bytes": (i32, [vp, i32, i32, C.POINTER(C.c_size_t)]),
             "clf_adjoint_forward": (i32, [vp, i32, i32, vp, C.c_size_t]),
             "clf_adjoint_backward": (i32, [vp, vp, i32, vp, vp, vp]),
+            "clf_bands_workspace_bytes": (i32, [C.POINTER(Grid), C.POINTER(Params), i32,
+                                                C.POINTER(C.c_size_t)]),
+            "clf_bands_init": (i32, [C.POINTER(vp), C.POINTER(Grid), vp, dbl, C.POINTER(Params),
+                                     i32, vp, vp, C.c_size_t]),
+            "clf_bands_set_initial": (i32, [vp, vp, vp, vp, i32]),
+            "clf_bands_step": (i32, [vp, i32]),
+            "clf_bands_get_state": (i32, [vp, vp, vp, vp, vp]),
+            "clf_bands_read_maxwave": (i32, [vp, vp, vp]),
+            "clf_bands_sync": (i32, [vp]),
+            "clf_bands_query": (i32, [vp, i32, C.POINTER(dbl)]),
+            "clf_bands_last_error": (C.c_char_p, [vp]),
+            "clf_bands_destroy": (i32, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -427,3 +442,95 @@ class Ensemble:
         v = C.c_double(0)
         self._chk(load().clf_ensemble_query(self._h, int(what), C.byref(v)), self._h)
         return v.value
+
+
+class Bands:
+    """One grid split into y-bands on one device (whole-grid arrays in and
+    out; the band layout stays inside the library)."""
+
+    def __init__(self, x, y, depth, dt, nbands, coord=CARTESIAN, precision=FP64, device=None,
+                 stream=None, **params):
+        import torch
+        self.torch = torch
+        L = load()
+        self.device = torch.device(device or "cuda")
+        depth = _np64(depth)
+        self.ny, self.nx = depth.shape
+        self._x, self._y = _np64(x), _np64(y)
+        self.grid = Grid(self.nx, self.ny, coord,
+                         self._x.ctypes.data_as(C.POINTER(C.c_double)),
+                         self._y.ctypes.data_as(C.POINTER(C.c_double)))
+        self.params = default_params(precision=precision, **params)
+        nbytes = C.c_size_t(0)
+        self._chk(L.clf_bands_workspace_bytes(C.byref(self.grid), C.byref(self.params),
+                                              int(nbands), C.byref(nbytes)), None)
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        self._chk(L.clf_bands_init(C.byref(h), C.byref(self.grid),
+                                   depth.ctypes.data_as(C.c_void_p), float(dt),
+                                   C.byref(self.params), int(nbands),
+                                   C.c_void_p(self.stream.cuda_stream),
+                                   C.c_void_p(self.workspace.data_ptr()), nbytes.value), None)
+        self._h = h
+
+    @classmethod
+    def from_case(cls, case, nbands, **kw):
+        kw.setdefault("h_min", case.h_min)
+        kw.setdefault("manning_n2", getattr(case, "manning_n2", 0.0))
+        kw.setdefault("friction_form", getattr(case, "friction_form", 0))
+        return cls(case.x, case.y, case.depth, case.dt, nbands, coord=case.coord, **kw)
+
+    def _chk(self, rc, h):
+        if rc != CLF_OK:
+            raise ClfError(rc, load().clf_bands_last_error(h).decode())
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.clf_bands_destroy(h)
+            self._h = None
+
+    def _dev64(self, a):
+        if a is None:
+            return None
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            a = a.to(device=self.device, dtype=t.float64)
+        else:
+            a = t.from_numpy(_np64(a)).to(self.device)
+        return a.reshape(self.ny, self.nx).contiguous()
+
+    def set_initial(self, eta=None, u=None, v=None, deform_bottom=False):
+        e, uu, vv = (self._dev64(a) for a in (eta, u, v))
+        self._chk(load().clf_bands_set_initial(self._h, _dptr(e), _dptr(uu), _dptr(vv),
+                                               int(bool(deform_bottom))), self._h)
+        self.torch.cuda.synchronize(self.device)
+
+    def step(self, n=1):
+        self._chk(load().clf_bands_step(self._h, int(n)), self._h)
+
+    def sync(self):
+        self._chk(load().clf_bands_sync(self._h), self._h)
+
+    def state(self):
+        t = self.torch
+        e, u, v = (t.empty((self.ny, self.nx), dtype=t.float64, device=self.device)
+                   for _ in range(3))
+        w = t.empty((self.ny, self.nx), dtype=t.uint8, device=self.device)
+        self._chk(load().clf_bands_get_state(self._h, _dptr(e), _dptr(u), _dptr(v), _dptr(w)),
+                  self._h)
+        return e, u, v, w
+
+    def read_maxwave(self):
+        t = self.torch
+        e, s = (t.empty((self.ny, self.nx), dtype=t.float64, device=self.device)
+                for _ in range(2))
+        self._chk(load().clf_bands_read_maxwave(self._h, _dptr(e), _dptr(s)), self._h)
+        return e, s
+
+    def query(self, what):
+        v = C.c_double(0)
+        self._chk(load().clf_bands_query(self._h, int(what), C.byref(v)), self._h)
+        return v.value
+

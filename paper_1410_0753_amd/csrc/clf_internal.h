@@ -140,6 +140,15 @@ hipError_t launch_forcing(int fp32, const GridDesc* gd_dev, const ForceDesc* fd_
 hipError_t launch_deform_depth(int fp32, const GridDesc* gd_host, const double* eta, long long N,
                                hipStream_t s);
 
+// One halo copy of a y-band decomposition: HALO rows of (h, u, v) from row
+// src_row of member src to row dst_row of member dst (rows of the members'
+// own grids).
+struct BandXchg {
+  int src, src_row, dst, dst_row;
+};
+hipError_t launch_band_exchange(int fp32, const GridDesc* grids, const BandXchg* xt, int nxchg,
+                                int nx, int parity, hipStream_t s);
+
 // Host helpers of the runtime (clf_runtime.cpp), shared with the
 // no-allocation entry point (clf_static.hip).
 struct GridMetrics {

@@ -1427,6 +1427,26 @@ __global__ void forcing_kernel(const GridDesc* grids, const ForceDesc* fd, long 
   }
 }
 
+// Halo rows of a y-band decomposition (one exchange per blockIdx.y): after a
+// step, the HALO rows beyond an inner band edge take the values of the band
+// that owns them.  Rows are contiguous, so each copy is HALO * nx elements
+// of each field.
+template <class R>
+__global__ void band_exchange_kernel(const GridDesc* grids, const BandXchg* xt, int nx,
+                                     int parity) {
+  const BandXchg x = xt[blockIdx.y];
+  const long long n = (long long)HALO * nx;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const GridDesc& gs = grids[x.src];
+  const GridDesc& gd = grids[x.dst];
+  const long long so = (long long)x.src_row * nx + k;
+  const long long dof = (long long)x.dst_row * nx + k;
+  ((R*)gd.H[parity])[dof] = ((const R*)gs.H[parity])[so];
+  ((R*)gd.U[parity])[dof] = ((const R*)gs.U[parity])[so];
+  ((R*)gd.V[parity])[dof] = ((const R*)gs.V[parity])[so];
+}
+
 inline int nblk(long long N, int bs) { return (int)((N + bs - 1) / bs); }
 
 }  // namespace
@@ -1617,6 +1637,18 @@ hipError_t launch_sample(int fp32, const GridDesc* gd, const SampleDesc* sd, int
 hipError_t launch_forcing(int fp32, const GridDesc* gd, const ForceDesc* fd, int nthreads,
                           long long n, int parity, hipStream_t s) {
   CLF_SMALL_LAUNCH(forcing_kernel, (long long)nthreads, gd, fd, n, parity);
+}
+
+hipError_t launch_band_exchange(int fp32, const GridDesc* grids, const BandXchg* xt, int nxchg,
+                                int nx, int parity, hipStream_t s) {
+  if (nxchg <= 0) return hipSuccess;
+  const int bs = 256;
+  dim3 grid(nblk((long long)HALO * nx, bs), nxchg);
+  if (fp32)
+    hipLaunchKernelGGL(band_exchange_kernel<float>, grid, dim3(bs), 0, s, grids, xt, nx, parity);
+  else
+    hipLaunchKernelGGL(band_exchange_kernel<double>, grid, dim3(bs), 0, s, grids, xt, nx, parity);
+  return hipGetLastError();
 }
 
 }  // namespace clf

@@ -717,6 +717,31 @@ int clf_workspace_bytes(const clf_grid* g, const clf_params* p, size_t* bytes) {
 
 // Set up one grid context in a workspace region.  with_tiles: build the
 // context's own tile list (and autotune); ensemble members skip it.
+// Still-water Courant number |lambda| dt / dx over wet nodes (stability
+// remark after solver2) and the smallest stability factor f_j (eq:f) of a
+// wet node between two wet line neighbours, along both axes.
+static void still_water_checks(int nx, int ny, const std::vector<double>& d, double dt,
+                               const GridMetrics& M, double* cmax_out, double* fmin_out) {
+  double cmax = 0.0, fmin = 1e300;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const double dd = d[(size_t)j * nx + i];
+      if (!(dd > 0.0)) continue;
+      const double cs = std::sqrt(kGrav * dd) * dt;
+      if (nx > 1) cmax = std::max(cmax, cs * M.xfac[j] * std::max(M.xib[i], M.xib[i + 1]));
+      if (ny > 1) cmax = std::max(cmax, cs * std::max(M.yib[j], M.yib[j + 1]));
+      auto fj = [&](double l, double r) {
+        if (l > 0.0 && r > 0.0)
+          fmin = std::min(fmin, (6.0 * std::sqrt(dd) - std::sqrt(l) - std::sqrt(r)) /
+                                    (4.0 * std::sqrt(dd)));
+      };
+      if (i > 0 && i + 1 < nx) fj(d[(size_t)j * nx + i - 1], d[(size_t)j * nx + i + 1]);
+      if (j > 0 && j + 1 < ny) fj(d[(size_t)(j - 1) * nx + i], d[(size_t)(j + 1) * nx + i]);
+    }
+  *cmax_out = cmax;
+  *fmin_out = fmin;
+}
+
 static int ctx_create(clf_ctx** out, const clf_grid* g, const double* depth, double dt,
                       const clf_params* p, void* stream, void* ws, size_t ws_bytes,
                       bool with_tiles) {
@@ -768,21 +793,7 @@ static int ctx_create(clf_ctx** out, const clf_grid* g, const double* depth, dou
 
   // still-water Courant number over wet nodes, and min f_j (eq:f)
   double cmax = 0.0, fmin = 1e300;
-  for (int j = 0; j < c->ny; ++j)
-    for (int i = 0; i < c->nx; ++i) {
-      const double dd = c->d[(size_t)j * c->nx + i];
-      if (!(dd > 0.0)) continue;
-      const double cs = std::sqrt(kGrav * dd) * dt;
-      if (c->nx > 1) cmax = std::max(cmax, cs * xfac[j] * std::max(xib[i], xib[i + 1]));
-      if (c->ny > 1) cmax = std::max(cmax, cs * std::max(yib[j], yib[j + 1]));
-      auto fj = [&](double l, double r) {
-        if (l > 0.0 && r > 0.0)
-          fmin = std::min(fmin, (6.0 * std::sqrt(dd) - std::sqrt(l) - std::sqrt(r)) /
-                                    (4.0 * std::sqrt(dd)));
-      };
-      if (i > 0 && i + 1 < c->nx) fj(c->d[(size_t)j * c->nx + i - 1], c->d[(size_t)j * c->nx + i + 1]);
-      if (j > 0 && j + 1 < c->ny) fj(c->d[(size_t)(j - 1) * c->nx + i], c->d[(size_t)(j + 1) * c->nx + i]);
-    }
+  still_water_checks(c->nx, c->ny, c->d, dt, M, &cmax, &fmin);
   c->max_cfl = cmax;
   c->min_f = fmin;
   if (cmax > p->cfl_limit) {
@@ -1864,6 +1875,285 @@ int clf_ensemble_destroy(clf_ens* e) {
   if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
   for (auto* c : e->m) clf_destroy(c);
   delete e;
+  return CLF_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// One grid split into y-bands on one device: the per-GPU part of the y-band
+// sharding of a large grid.  Each band is an ensemble member holding its own
+// rows plus HALO rows beyond each inner edge.  One step is one step-kernel
+// launch over every band's tiles followed by one exchange launch: the HALO
+// rows beyond each inner edge take the post-step values of the band that owns
+// them.  A node's update depends on the pre-step state within HALO rows
+// (steps (a)-(e) of the y-sweep reach 3 nodes; the x-sweep is row-local), so
+// the owned rows of every band are exactly the whole-grid run's, and after
+// the exchange so are the halo rows.
+// ===========================================================================
+struct clf_bands {
+  clf_ens* e = nullptr;
+  hipStream_t stream = nullptr;
+  int nx = 0, ny = 0, fp32 = 0;
+  std::vector<int> r0, r1, g0;  // owned rows [r0, r1); first row of the band's grid g0
+  BandXchg* xt_dev = nullptr;
+  int nxchg = 0;
+  int ssl_passes = 0;
+  double max_cfl = 0, min_f = 0;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_band_error;
+
+int bfail(clf_bands* b, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (b) b->err = buf;
+  else g_band_error = buf;
+  return code;
+}
+
+struct BandPlan {
+  std::vector<int> r0, r1, g0, g1;
+  std::vector<std::vector<double>> ys;
+  std::vector<clf_grid> grids;
+  EnsPlan E;
+  size_t xt = 0, total = 0;
+};
+
+clf_params band_member_params(const clf_params& p) {
+  clf_params q = p;
+  q.ssl_alpha = 0.0;     // the whole grid's depth is preprocessed once
+  q.cfl_limit = 1e300;   // and checked once, on the whole grid
+  return q;
+}
+
+int band_plan(const clf_grid* g, const clf_params* p, int nb, BandPlan& P) {
+  int rc = validate(g, p, nullptr);
+  if (rc) return bfail(nullptr, rc, "%s", g_init_error.c_str());
+  if (g->nx < 3 || g->ny < 3) return bfail(nullptr, CLF_EINVAL, "bands need a 2-D grid");
+  if (p->sweep_order != CLF_ORDER_XY) return bfail(nullptr, CLF_EINVAL, "bands use the x-y order");
+  if (nb < 1 || g->ny / nb < HALO)
+    return bfail(nullptr, CLF_EINVAL, "%d bands of %d rows: every band needs %d rows or more", nb,
+                 g->ny, HALO);
+  const int base = g->ny / nb, extra = g->ny % nb;
+  int r = 0;
+  for (int b = 0; b < nb; ++b) {
+    const int rows = base + (b < extra ? 1 : 0);
+    P.r0.push_back(r);
+    P.r1.push_back(r + rows);
+    P.g0.push_back(std::max(0, r - HALO));
+    P.g1.push_back(std::min(g->ny, r + rows + HALO));
+    r += rows;
+  }
+  for (int b = 0; b < nb; ++b) P.ys.emplace_back(g->y + P.g0[b], g->y + P.g1[b]);
+  for (int b = 0; b < nb; ++b)
+    P.grids.push_back(clf_grid{g->nx, P.g1[b] - P.g0[b], g->coord, g->x, P.ys[b].data()});
+  P.E = ens_plan(nb, P.grids.data(), band_member_params(*p));
+  P.xt = align_up(P.E.total, 256);
+  P.total = align_up(P.xt + sizeof(BandXchg) * 2 * (size_t)nb, 256);
+  return CLF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int clf_bands_workspace_bytes(const clf_grid* g, const clf_params* p, int nbands, size_t* bytes) {
+  if (!g || !p || !bytes) return bfail(nullptr, CLF_EINVAL, "null argument");
+  BandPlan P;
+  int rc = band_plan(g, p, nbands, P);
+  if (rc) return rc;
+  *bytes = P.total;
+  return CLF_OK;
+}
+
+int clf_bands_init(clf_bands** out, const clf_grid* g, const double* depth, double dt,
+                   const clf_params* p, int nbands, void* stream, void* ws, size_t ws_bytes) {
+  TraceRange trace_("clf_bands_init");
+  if (!out) return bfail(nullptr, CLF_EINVAL, "null output");
+  *out = nullptr;
+  if (!g || !p || !depth || !ws) return bfail(nullptr, CLF_EINVAL, "null argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return bfail(nullptr, CLF_EINVAL, "dt must be > 0");
+  BandPlan P;
+  int rc = band_plan(g, p, nbands, P);
+  if (rc) return rc;
+  if (ws_bytes < P.total)
+    return bfail(nullptr, CLF_ENOSPACE, "workspace too small: %zu < %zu", ws_bytes, P.total);
+  if (((uintptr_t)ws) % 256 != 0) return bfail(nullptr, CLF_EINVAL, "workspace not aligned");
+  const size_t N = (size_t)g->nx * g->ny;
+  std::vector<double> d(depth, depth + N);
+  for (double v : d)
+    if (!std::isfinite(v)) return bfail(nullptr, CLF_EINVAL, "non-finite depth");
+  int passes = 0;
+  if (p->ssl_alpha > 0.0) {
+    passes = preprocess_depth(g->nx, g->ny, d, p->ssl_alpha, p->ssl_min_depth);
+    if (passes < 0)
+      return bfail(nullptr, CLF_ESSL, "depth preprocessing did not converge in 1000 passes");
+  }
+  GridMetrics M;
+  build_metrics(*g, *p, M);
+  double cmax = 0.0, fmin = 1e300;
+  still_water_checks(g->nx, g->ny, d, dt, M, &cmax, &fmin);
+  if (cmax > p->cfl_limit)
+    return bfail(nullptr, CLF_ECFL, "still-water Courant number %.4f exceeds %.4f", cmax,
+                 p->cfl_limit);
+  std::vector<const double*> depths;
+  std::vector<double> dts(nbands, dt);
+  for (int b = 0; b < nbands; ++b) depths.push_back(d.data() + (size_t)P.g0[b] * g->nx);
+  const clf_params q = band_member_params(*p);
+  clf_ens* e = nullptr;
+  rc = clf_ensemble_init(&e, nbands, P.grids.data(), depths.data(), dts.data(), &q, stream, ws,
+                         P.E.total);
+  if (rc) return bfail(nullptr, rc, "%s", g_ens_error.c_str());
+  clf_bands* bd = new clf_bands();
+  bd->e = e;
+  bd->stream = (hipStream_t)stream;
+  bd->nx = g->nx;
+  bd->ny = g->ny;
+  bd->fp32 = e->fp32;
+  bd->r0 = P.r0;
+  bd->r1 = P.r1;
+  bd->g0 = P.g0;
+  bd->ssl_passes = passes;
+  bd->max_cfl = cmax;
+  bd->min_f = fmin;
+  // each inner edge: the lower band's last HALO owned rows become the upper
+  // band's first (halo) rows, and the upper band's first HALO owned rows the
+  // lower band's last (halo) rows
+  std::vector<BandXchg> xt;
+  for (int b = 0; b + 1 < nbands; ++b) {
+    const int edge = P.r1[b];
+    xt.push_back(BandXchg{b, edge - HALO - P.g0[b], b + 1, edge - HALO - P.g0[b + 1]});
+    xt.push_back(BandXchg{b + 1, edge - P.g0[b + 1], b, edge - P.g0[b]});
+  }
+  bd->nxchg = (int)xt.size();
+  bd->xt_dev = (BandXchg*)((char*)ws + P.xt);
+  hipError_t he = hipSuccess;
+  if (!xt.empty())
+    he = hipMemcpyAsync(bd->xt_dev, xt.data(), xt.size() * sizeof(BandXchg),
+                        hipMemcpyHostToDevice, bd->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(bd->stream);
+  if (he != hipSuccess) {
+    clf_bands_destroy(bd);
+    return bfail(nullptr, CLF_EHIP, "exchange table upload: %s", hipGetErrorString(he));
+  }
+  *out = bd;
+  return CLF_OK;
+}
+
+int clf_bands_set_initial(clf_bands* b, const double* eta, const double* u, const double* v,
+                          int deform_bottom) {
+  if (!b) return CLF_EINVAL;
+  const size_t nx = b->nx;
+  for (int k = 0; k < (int)b->r0.size(); ++k) {
+    const size_t off = (size_t)b->g0[k] * nx;
+    int rc = clf_ensemble_set_initial(b->e, k, eta ? eta + off : nullptr, u ? u + off : nullptr,
+                                      v ? v + off : nullptr, deform_bottom);
+    if (rc) return bfail(b, rc, "%s", b->e->err.c_str());
+  }
+  b->e->n = 0;
+  return CLF_OK;
+}
+
+int clf_bands_step(clf_bands* b, int nsteps) {
+  TraceRange trace_("clf_bands_step");
+  if (!b) return CLF_EINVAL;
+  if (nsteps < 0) return bfail(b, CLF_EINVAL, "negative step count");
+  clf_ens* e = b->e;
+  const int nb = eff_blocks(e->nblocks, e->p.persistent_blocks);
+  for (int k = 0; k < nsteps; ++k) {
+    const int do_max = ((e->n + 1) % e->p.maxout) == 0;
+    hipError_t he = launch_step(e->fp32, ORD_XY, e->gflags, e->gd_dev, e->tiles_dev, e->ntiles,
+                                e->st_dev, e->cur, do_max, nb, b->stream);
+    e->cur ^= 1;
+    e->n += 1;
+    if (he == hipSuccess)
+      he = launch_band_exchange(e->fp32, e->gd_dev, b->xt_dev, b->nxchg, b->nx, e->cur, b->stream);
+    if (he != hipSuccess) return bfail(b, CLF_EHIP, "band step: %s", hipGetErrorString(he));
+  }
+  return CLF_OK;
+}
+
+int clf_bands_sync(clf_bands* b) {
+  if (!b) return CLF_EINVAL;
+  int rc = clf_ensemble_sync(b->e);
+  return rc ? bfail(b, rc, "%s", b->e->err.c_str()) : CLF_OK;
+}
+
+// The owned rows of band k as a grid descriptor of their own (field pointers
+// advanced to the first owned row).
+static GridDesc owned_rows(const clf_bands* b, int k, long long* N) {
+  const clf_ctx* c = b->e->m[k];
+  GridDesc gd = c->gd;
+  const size_t es = b->fp32 ? 4 : 8;
+  const size_t off = (size_t)(b->r0[k] - b->g0[k]) * b->nx * es;
+  auto adv = [&](void* ptr) { return (void*)((char*)ptr + off); };
+  for (int q = 0; q < 2; ++q) {
+    gd.H[q] = adv(gd.H[q]);
+    gd.U[q] = adv(gd.U[q]);
+    gd.V[q] = adv(gd.V[q]);
+  }
+  gd.D = adv(gd.D);
+  gd.emax = adv(gd.emax);
+  gd.smax2 = adv(gd.smax2);
+  *N = (long long)(b->r1[k] - b->r0[k]) * b->nx;
+  return gd;
+}
+
+int clf_bands_get_state(clf_bands* b, double* eta, double* u, double* v, uint8_t* wet) {
+  if (!b) return CLF_EINVAL;
+  for (int k = 0; k < (int)b->r0.size(); ++k) {
+    long long N = 0;
+    const GridDesc gd = owned_rows(b, k, &N);
+    const size_t o = (size_t)b->r0[k] * b->nx;
+    hipError_t he = launch_get_state(b->fp32, &gd, nullptr, eta ? eta + o : nullptr,
+                                     u ? u + o : nullptr, v ? v + o : nullptr,
+                                     wet ? wet + o : nullptr, N, b->e->cur, b->stream);
+    if (he != hipSuccess) return bfail(b, CLF_EHIP, "get state: %s", hipGetErrorString(he));
+  }
+  return clf_bands_sync(b);
+}
+
+int clf_bands_read_maxwave(clf_bands* b, double* eta_max, double* speed_max) {
+  if (!b) return CLF_EINVAL;
+  for (int k = 0; k < (int)b->r0.size(); ++k) {
+    long long N = 0;
+    const GridDesc gd = owned_rows(b, k, &N);
+    const size_t o = (size_t)b->r0[k] * b->nx;
+    hipError_t he = launch_read_maxwave(b->fp32, &gd, nullptr, eta_max ? eta_max + o : nullptr,
+                                        speed_max ? speed_max + o : nullptr, N, b->stream);
+    if (he != hipSuccess) return bfail(b, CLF_EHIP, "read maxwave: %s", hipGetErrorString(he));
+  }
+  return clf_bands_sync(b);
+}
+
+int clf_bands_query(clf_bands* b, int what, double* value) {
+  if (!b || !value) return CLF_EINVAL;
+  switch (what) {
+    case CLF_Q_MAX_CFL: *value = b->max_cfl; return CLF_OK;
+    case CLF_Q_MIN_F: *value = b->min_f; return CLF_OK;
+    case CLF_Q_SSL_PASSES: *value = b->ssl_passes; return CLF_OK;
+    default: {
+      int rc = clf_ensemble_query(b->e, what, value);
+      return rc ? bfail(b, rc, "%s", b->e->err.c_str()) : CLF_OK;
+    }
+  }
+}
+
+const char* clf_bands_last_error(const clf_bands* b) {
+  return b ? b->err.c_str() : g_band_error.c_str();
+}
+
+int clf_bands_destroy(clf_bands* b) {
+  if (!b) return CLF_EINVAL;
+  if (b->e) clf_ensemble_destroy(b->e);
+  delete b;
   return CLF_OK;
 }
 
