@@ -254,6 +254,50 @@ const char* clf_last_error(const clf_ctx* c);
 int clf_destroy(clf_ctx* c);
 
 /* ------------------------------------------------------------------------
+ * No-allocation variant of clf_step, for callers that cannot allocate: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It runs the same split step (same kernels, same results bit for
+ * bit as clf_step on a context with the same grid, depth and parameters) on
+ * state arrays the caller owns, and needs no context and no workspace: the
+ * grid descriptor, the non-finite flag, the metric arrays and the tile list
+ * go into a fixed static scratch array of 4 MiB on each GPU (held until the
+ * process ends).  The call allocates no device memory and calls no
+ * allocating routine.
+ *
+ *   g, p, dt   grid, parameters and time step as for clf_init.  Not done
+ *              here: depth preprocessing (pass a preprocessed depth, e.g. from
+ *              clf_get_depth of a context), the Courant check, forcing,
+ *              gauges, enclosed grids; p->sweep_order must be CLF_ORDER_XY.
+ *   depth      device [ny][nx] in the storage precision (double for CLF_FP64,
+ *              float for CLF_FP32), +down, used as given.
+ *   h_a,u_a,v_a, h_b,u_b,v_b
+ *              two device state buffers [ny][nx] in the storage form: FP64
+ *              h, u, v as double; FP32 eta = h - d (dry nodes hold -d), u, v
+ *              as float.  Buffer A holds the state on entry; the steps
+ *              alternate A -> B -> A ..., so on return the state is in A if
+ *              nsteps is even and in B if it is odd.  Buffers must not overlap.
+ *   eta_max, speed2_max
+ *              device [ny][nx] running maxima (storage precision) of eta and
+ *              of u^2 + v^2 over wet nodes, updated after every step; both
+ *              NULL to skip.  The caller initialises them (zeros).
+ *   nsteps     steps to take (>= 0).
+ *   stream     hipStream_t (as void*) on the current device; the call is
+ *              asynchronous unless nonfinite is given.
+ *   nonfinite  NULL, or a host int that receives 1 if the state went
+ *              non-finite during the call (the call then waits for the stream).
+ *
+ * Returns CLF_EINVAL for bad arguments, CLF_ENOSPACE when the grid's metric
+ * arrays and tile list do not fit the 4 MiB scratch (about nx + ny above
+ * 100000 in FP64), CLF_EHIP on a runtime error; clf_last_error(NULL) gives
+ * the message.  All calls on one GPU share its scratch, which keeps the last
+ * call's contents (a call that repeats the previous call's grid and buffers
+ * uploads nothing): calls that overlap on one GPU, on different streams or
+ * threads, race. */
+int clf_step_static(const clf_grid* g, const clf_params* p, double dt, const void* depth,
+                    void* h_a, void* u_a, void* v_a, void* h_b, void* u_b, void* v_b,
+                    void* eta_max, void* speed2_max, int nsteps, void* stream, int* nonfinite);
+
+/* ------------------------------------------------------------------------
  * Adjoint (reverse mode) of the FP64 split step, for gradients of a loss of
  * the gauge records with respect to the initial state (source inversion).
  * The branch decisions of the wet/dry cycle and of stateh are frozen at the

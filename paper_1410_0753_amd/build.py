@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libclf.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(CSRC, "clf_kernels.hip"), os.path.join(CSRC, "clf_adjoint.hip"),
-           os.path.join(CSRC, "clf_runtime.cpp")]
+           os.path.join(CSRC, "clf_runtime.cpp"), os.path.join(CSRC, "clf_static.hip")]
 ARCH = os.environ.get("CLF_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",

@@ -38,7 +38,7 @@ EXPORTS = ["clf_default_params", "clf_node_index", "clf_workspace_bytes", "clf_i
            "clf_ensemble_step", "clf_ensemble_get_state", "clf_ensemble_read_maxwave",
            "clf_ensemble_sync", "clf_ensemble_query", "clf_ensemble_last_error",
            "clf_ensemble_destroy", "clf_adjoint_workspace_bytes", "clf_adjoint_forward",
-           "clf_adjoint_backward", "clf_bands_workspace_bytes",
+           "clf_adjoint_backward", "clf_step_static", "clf_bands_workspace_bytes",
            "clf_bands_init", "clf_bands_set_initial", "clf_bands_step", "clf_bands_get_state",
            "clf_bands_read_maxwave", "clf_bands_sync", "clf_bands_query",
            "clf_bands_last_error", "clf_bands_destroy"]
@@ -124,6 +124,8 @@ def load(build_if_missing: bool = True):
             "clf_adjoint_workspace_bytes": (i32, [vp, i32, i32, C.POINTER(C.c_size_t)]),
             "clf_adjoint_forward": (i32, [vp, i32, i32, vp, C.c_size_t]),
             "clf_adjoint_backward": (i32, [vp, vp, i32, vp, vp, vp]),
+            "clf_step_static": (i32, [C.POINTER(Grid), C.POINTER(Params), dbl, vp, vp, vp, vp,
+                                      vp, vp, vp, vp, vp, i32, vp, C.POINTER(i32)]),
             "clf_bands_workspace_bytes": (i32, [C.POINTER(Grid), C.POINTER(Params), i32,
                                                 C.POINTER(C.c_size_t)]),
             "clf_bands_init": (i32, [C.POINTER(vp), C.POINTER(Grid), vp, dbl, C.POINTER(Params),
@@ -534,3 +536,29 @@ class Bands:
         self._chk(load().clf_bands_query(self._h, int(what), C.byref(v)), self._h)
         return v.value
 
+
+def step_static(x, y, coord, depth, a, b, nsteps, dt, eta_max=None, speed2_max=None,
+                stream=None, check=True, **params):
+    """clf_step_static on torch tensors (argument marshalling only).
+
+    depth: device tensor [ny, nx] in the storage precision; a, b: (h, u, v)
+    tuples of device tensors in the storage form (FP64 h; FP32 eta with dry
+    nodes at -d).  Returns the index (0 for a, 1 for b) of the buffer that
+    holds the final state, and the non-finite flag when `check`."""
+    import torch
+    L = load()
+    x, y = _np64(x), _np64(y)
+    ny, nx = depth.shape
+    grid = Grid(nx, ny, coord, x.ctypes.data_as(C.POINTER(C.c_double)),
+                y.ctypes.data_as(C.POINTER(C.c_double)))
+    p = default_params(**params)
+    st = stream if stream is not None else torch.cuda.current_stream(depth.device)
+    flag = C.c_int(0)
+    ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+    rc = L.clf_step_static(C.byref(grid), C.byref(p), float(dt), ptr(depth),
+                           *(ptr(t) for t in a), *(ptr(t) for t in b), ptr(eta_max),
+                           ptr(speed2_max), int(nsteps), C.c_void_p(st.cuda_stream),
+                           C.byref(flag) if check else None)
+    if rc != CLF_OK:
+        raise ClfError(rc, L.clf_last_error(None).decode())
+    return nsteps % 2, (bool(flag.value) if check else None)
