@@ -1,42 +1,48 @@
 """Benchmark of the split step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload c2|c5|c1|ensemble|adjoint|c5err]
+                    [--workload c5|c2|c1|ensemble|adjoint|c5search]
                     [--precision fp64|fp32] [--no-cpu] [--no-extras] [--profile]
+                    [--calibrate-copy]
 
-Headline (default): the 2400 x 1800 spherical grid at 1 arc-minute (seeded
-synthetic coast, shelf, slope and dipole source; 50 gauges every 10 steps;
-maxwave every step) in FP64.  A step is one full split step (x-sweep of every
-row, y-sweep of every column, wet/dry cycle, maxwave, gauge records) of the
-whole grid with the state resident in HBM.  Prints ONE JSON line.
+Headline (default): the 8000 x 6000 spherical grid at 0.5 arc-minute (seeded
+synthetic coast, shelf, slope, plane beaches at 1:50 and islands; 3 m dipole
+source; explicit Manning friction; 50 gauges every 10 steps; maxwave every
+step; the boundary series of 4 enclosed 400 x 400 grids every step) in FP64.
+Its field arrays (3.5 GB in FP64) are far beyond the 256 MB Infinity Cache,
+so the step streams from HBM.  A step is one full split step (x-sweep of
+every row, y-sweep of every column, wet/dry cycle, maxwave, gauge and
+series records) of the whole grid with the state resident in HBM.  Prints
+ONE JSON line.
 
-value = cell-updates/s = nx * ny * K / (time of K steps), timed with HIP
-events on the library's stream, bracketed by device synchronisation.
+value = nx * ny * K / (time of K steps), timed with HIP events on the
+library's stream, bracketed by device synchronisation.
 
-roofline: the fused step kernel alone is timed over K launches with HIP
-events on its stream; achieved = algorithmic bytes per launch / mean launch
-time, where one cell-step moves 11 words (read h, u, v, d; write h, u, v;
-read and write the two maxwave arrays): 88 B in FP64, 44 B in FP32.
-peak = 8 TB/s; copy_GBps is a measured 1 GiB device copy on the same GPU
-(what a plain streaming kernel attains).  `traffic` is the calibrated
-rocprofv3 FETCH_SIZE + WRITE_SIZE of the kernel per launch when the kernel
-source is the one that was profiled (else null).
+roofline: the library records a HIP event pair around every step-kernel
+launch of the timed steps (kernel_timing); achieved = algorithmic bytes per
+launch / mean launch time, where one cell-step moves 11 words (read h, u, v,
+d; write h, u, v; read and write the two maxwave arrays): 88 B in FP64, 44 B
+in FP32.  peak = 8 TB/s; copy_GBps and read_GBps are the best rates of the
+streaming probes (libclf_probe.so) over a sweep of launch shapes on the same
+GPU.  `traffic` is the calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE of the
+kernel per launch when the kernel source and launch shape are the ones that
+were profiled (else null).
 
 cpu_baseline: the FP64 oracle (OpenMP over rows / columns) on this host, on
 a bounded number of full steps of the same grid, plus a shorter
 single-thread sample.
 
-extras (same line): the FP32 run of the headline grid with its error
-against the FP64 oracle; the 8000 x 6000 spherical grid (FP32 and FP64, with
-its 4 enclosed-grid boundary series every step); the 64-member
-ensemble against sequential single-grid solves; the adjoint gradient of the
-1000 x 800 inversion problem against a finite-difference gradient (and an
-estimate of the same gradient by the host oracle); the oracle's rate on the
-200 x 200 and 8000 x 6000 grids.
+extras (same line): the FP32 run of the headline grid, with its error
+against the FP64 oracle after a bounded number of steps and against the FP64
+GPU path (bitwise equal to the oracle on the parity tests) over the whole
+20000-step run, including the ever-wet masks of initially dry nodes; the
+2400 x 1800 grid (FP64 and FP32, cache-resident); the 64-member ensemble
+against sequential single-grid solves; the adjoint gradient of the 1000 x 800
+inversion problem against a finite-difference gradient.
 
---workload c5err (not part of the default run) reports the FP32 error on the
-8000 x 6000 grid: against the FP64 oracle after min(K, 50) steps and against
-the FP64 GPU path after K steps.
+--workload c5search (not part of the default run) measures the fraction of
+initially dry nodes that are ever wet over the whole 8000 x 6000 run for a
+range of dipole amplitudes (FP32).
 """
 from __future__ import annotations
 
@@ -83,15 +89,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_case(name, steps):
+def make_case(name, steps=None):
     from paper_1410_0753_amd import synth
     if name == "c2":
-        return synth.config2(steps=steps)
+        return synth.config2() if steps is None else synth.config2(steps=steps)
     if name == "c5":
-        return synth.config5(steps=steps)
+        return synth.config5() if steps is None else synth.config5(steps=steps)
     if name == "c1":
-        return synth.config1(steps=steps)
+        return synth.config1() if steps is None else synth.config1(steps=steps)
     raise SystemExit("unknown workload " + name)
+
+
+def workload_label(case, prec, enclosed):
+    fric = ("Manning n^2 = %g, explicit -alpha dt friction capped at the velocity"
+            % case.manning_n2) if case.manning_n2 > 0 else "no friction"
+    out = "%s (%s, %s, 50 gauges every 10 steps, maxwave every step" % (case.name, prec, fric)
+    if enclosed and case.enclosed:
+        out += ", boundary series of %d enclosed grids every step" % len(case.enclosed)
+    return out + ")"
 
 
 def kernel_sha():
@@ -111,85 +126,155 @@ def timed(torch, stream, fn):
 
 
 def run_grid(case, prec, steps, warmup, gauges=True, enclosed=False, bndout=1):
-    """Whole-step throughput (with gauges, and the enclosed-grid boundary
-    series every `bndout` steps when `enclosed`) and the step kernel alone."""
+    """Whole-step throughput (gauges every 10 steps, maxwave every step, and
+    the enclosed-grid boundary series every `bndout` steps when `enclosed`),
+    with the step kernel's own launches timed by the library's event pairs
+    over the same timed steps."""
     import torch
     from paper_1410_0753_amd import clf
     esize = 4 if prec == clf.FP32 else 8
     kw = {}
     if enclosed and case.enclosed:
         kw = dict(bndout=bndout, max_enclosed=len(case.enclosed),
+                  max_enclosed_points=sum(2 * (len(x) + len(y)) for x, y in case.enclosed),
                   series_capacity=(steps + warmup) // bndout + 8)
     s = clf.Solver.from_case(case, precision=prec, gout=10, maxout=1, autotune=1,
-                             gauge_capacity=(steps + warmup) // 10 + 8, **kw)
+                             kernel_timing=1, gauge_capacity=(steps + warmup) // 10 + 8, **kw)
     s.set_initial(case.eta0, case.u0, case.v0)
     if gauges and case.gauges is not None:
         s.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
     if kw:
         for ex, ey in case.enclosed:
             s.add_enclosed_grid(ex, ey)
-    dry0 = s.state()[3] == 0
     seg = int(s.query(clf.Q_SEGMENT))
     s.step(warmup)
     s.sync()
+    s.query(clf.Q_KERNEL_RESET)
     secs = timed(torch, s.stream, lambda: s.step(steps))
     s.sync()
+    kernel_ms = s.query(clf.Q_KERNEL_MS)
+    launches = int(s.query(clf.Q_KERNEL_LAUNCHES))
     e, _, _, w = s.state()
-    emax = s.read_maxwave()[0]
-    ever_wet = float(((emax > 0) & dry0).sum()) / max(1.0, float(dry0.sum()))
-    log("%s %s: %.4f ms/step, segment %d, max|eta| %.3f, wet %d" % (
-        case.name, "fp32" if prec == clf.FP32 else "fp64", secs / steps * 1e3, seg,
-        float(e.abs().max()), int(w.sum())))
+    log("%s %s: %.4f ms/step, kernel %.4f ms (%d launches), segment %d, max|eta| %.3f, wet %d" % (
+        case.name, "fp32" if prec == clf.FP32 else "fp64", secs / steps * 1e3, kernel_ms,
+        launches, seg, float(e.abs().max()), int(w.sum())))
+    achieved = WORDS_PER_CELL_STEP * esize * case.cells / (kernel_ms * 1e-3)
+    blocks = int(s.query(clf.Q_BLOCKS))
     del s
-    r = clf.Solver.from_case(case, precision=prec, maxout=1, autotune=1, graph_steps=0)
-    r.set_initial(case.eta0, case.u0, case.v0)
-    r.step(warmup)
-    r.sync()
-    ksecs = timed(torch, r.stream, lambda: r.step(steps))
-    r.sync()
-    per_launch = ksecs / steps
-    achieved = WORDS_PER_CELL_STEP * esize * case.cells / per_launch
-    blocks = int(r.query(clf.Q_BLOCKS))
-    del r
     return {"value": case.cells * steps / secs, "ms_per_step": secs / steps * 1e3,
-            "segment": seg, "kernel_ms": per_launch * 1e3, "achieved": achieved,
-            "workgroups": blocks,
-            "ever_wet_frac_of_initially_dry": ever_wet,
+            "segment": seg, "kernel_ms": kernel_ms, "kernel_launches": launches,
+            "achieved": achieved, "workgroups": blocks,
             "enclosed_grids": len(case.enclosed) if kw else 0}
 
 
-def copy_bandwidth():
-    """Device-to-device copy of 1 GiB (read + write bytes / time): the
-    attainable HBM rate of a plain streaming kernel on this GPU."""
+def probe_rates():
+    """Best copy and read rates of the streaming probes over launch shapes
+    (1 GiB buffers; copy counts bytes read + written)."""
+    import ctypes
     import torch
-    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    from paper_1410_0753_amd import build
+    L = ctypes.CDLL(build.PROBE_LIB)
+    L.clf_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_void_p]
+    L.clf_probe_read.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                 ctypes.c_uint, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    nbytes = 1 << 30
+    a = torch.full((nbytes,), 1, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
-    reps = 10
+    sink = torch.zeros(4, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
-    secs = timed(torch, stream, lambda: [b.copy_(a) for _ in range(reps)])
-    del a, b
-    return 2.0 * (1 << 30) * reps / secs
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    out = {}
+    for kind in ("copy", "read"):
+        best = (0.0, None)
+        for blocks in (1024, 2048, 4096, 8192, 16384, 32768):
+            for threads in (256, 512):
+                def go():
+                    for _ in range(5):
+                        rc = (L.clf_probe_copy(a.data_ptr(), b.data_ptr(), nbytes, blocks, threads, sp)
+                              if kind == "copy" else
+                              L.clf_probe_read(a.data_ptr(), nbytes, sink.data_ptr(), 0xDEADBEEF,
+                                               blocks, threads, sp))
+                        assert rc == 0, rc
+                go()
+                secs = timed(torch, stream, go)
+                rate = (2 if kind == "copy" else 1) * nbytes * 5 / secs
+                if rate > best[0]:
+                    best = (rate, [blocks, threads])
+        out[kind] = best
+    del a, b, sink
+    return {"copy_GBps": out["copy"][0] / 1e9, "copy_shape": out["copy"][1],
+            "read_GBps": out["read"][0] / 1e9, "read_shape": out["read"][1]}
 
 
-def fp32_error(case, steps):
-    """FP32 GPU vs FP64 oracle after `steps` steps: max/RMS eta error over the
-    amplitude, fraction of nodes whose wet flag differs."""
+def _final_fields(case, prec, nsteps, **kw):
+    """Run `nsteps` steps from the case's initial state; return (eta, wet,
+    ever-wet of initially dry nodes, initially dry) as numpy arrays."""
     import numpy as np
+    from paper_1410_0753_amd import clf
+    s = clf.Solver.from_case(case, precision=prec, maxout=1, autotune=1, **kw)
+    s.set_initial(case.eta0, case.u0, case.v0)
+    dry0 = (s.state()[3] == 0).cpu().numpy()
+    s.step(nsteps)
+    e, _, _, w = (t.cpu().numpy() for t in s.state())
+    em = s.read_maxwave()[0].cpu().numpy()
+    del s
+    return e, w.astype(bool), (em > 0) & dry0, dry0
+
+
+def _compare(ea, wa, eb, wb):
+    import numpy as np
+    amp = float(np.abs(eb).max())
+    err = np.abs(ea - eb)
+    return {"max_eta_err_rel": float(err.max() / amp),
+            "rms_eta_err_rel": float(np.sqrt((err ** 2).mean()) / amp),
+            "mask_flip_frac": float((wa != wb).mean())}
+
+
+def fp32_report(case, oracle_steps):
+    """The FP32 path against the FP64 oracle after `oracle_steps` steps, and
+    against the FP64 GPU path over the whole run (case.steps), with the
+    ever-wet masks of initially dry nodes."""
     import oracle
     from paper_1410_0753_amd import clf
-    g = clf.Solver.from_case(case, precision=clf.FP32)
+    log("fp32 vs fp64 oracle, %d steps ..." % oracle_steps)
+    e32, w32, _, _ = _final_fields(case, clf.FP32, oracle_steps)
     o = oracle.Oracle.from_case(case)
-    for obj in (g, o):
-        obj.set_initial(case.eta0, case.u0, case.v0)
-        obj.step(steps)
-    eg, _, _, wg = (t.cpu().numpy() for t in g.state())
+    o.set_initial(case.eta0, case.u0, case.v0)
+    t0 = time.perf_counter()
+    o.step(oracle_steps)
+    t_ora = time.perf_counter() - t0
     eo, _, _, wo = o.state()
-    amp = float(np.abs(eo).max())
-    err = np.abs(eg - eo)
-    return {"steps": steps, "max_eta_err_rel": float(err.max() / amp),
-            "rms_eta_err_rel": float(np.sqrt((err ** 2).mean()) / amp),
-            "mask_flip_frac": float((wg.astype(bool) != wo.astype(bool)).mean())}
+    del o
+    res = {"vs_fp64_oracle": dict(steps=oracle_steps, oracle_s=t_ora,
+                                  **_compare(e32, w32, eo, wo.astype(bool)))}
+    log("fp32 vs fp64 gpu, whole run of %d steps ..." % case.steps)
+    e32, w32, ew32, dry0 = _final_fields(case, clf.FP32, case.steps)
+    e64, w64, ew64, _ = _final_fields(case, clf.FP64, case.steps)
+    r = dict(steps=case.steps, **_compare(e32, w32, e64, w64))
+    ndry = max(1, int(dry0.sum()))
+    r["initially_dry_nodes"] = ndry
+    r["ever_wet_of_initially_dry_fp64"] = float(ew64.sum() / ndry)
+    r["ever_wet_of_initially_dry_fp32"] = float(ew32.sum() / ndry)
+    r["ever_wet_flip_frac_of_initially_dry"] = float((ew32 != ew64).sum() / ndry)
+    res["vs_fp64_gpu"] = r
+    return res
+
+
+def c5_amplitude_search(amps=(3.0, 4.5, 6.0, 8.0, 10.0, 12.0)):
+    """Fraction of initially dry nodes ever wet over the whole 8000 x 6000 run
+    (FP32) for a range of dipole amplitudes (the source scales linearly)."""
+    from paper_1410_0753_amd import clf, synth
+    base = synth.config5()
+    out = []
+    eta3 = base.eta0
+    for amp in amps:
+        base.eta0 = synth.f32(eta3 * (amp / 3.0))
+        _, _, ew, dry0 = _final_fields(base, clf.FP32, base.steps)
+        frac = float(ew.sum() / max(1, dry0.sum()))
+        log("amplitude %.1f m: ever-wet %.4f of %d initially dry nodes" % (amp, frac, dry0.sum()))
+        out.append({"amplitude_m": amp, "ever_wet_of_initially_dry": frac})
+    return {"workload": base.name, "steps": base.steps, "precision": "fp32", "scan": out}
 
 
 def run_ensemble(steps, n=64):
@@ -339,74 +424,27 @@ def cpu_other(cases):
     return out
 
 
-def fp32_error_large(steps, oracle_steps):
-    """FP32 on the 8000x6000 grid against the FP64 oracle after
-    `oracle_steps` steps, and against the FP64 GPU path (bitwise equal to the
-    oracle on every parity test) after `steps` steps."""
-    import numpy as np
-    import oracle
-    from paper_1410_0753_amd import clf, synth
-    case = synth.config5(steps=steps)
-
-    def run(prec, n):
-        s = clf.Solver.from_case(case, precision=prec, maxout=1, autotune=1)
-        s.set_initial(case.eta0, case.u0, case.v0)
-        dry0 = (s.state()[3] == 0).cpu().numpy()
-        s.step(n)
-        e, _, _, w = (t.cpu().numpy() for t in s.state())
-        em = s.read_maxwave()[0].cpu().numpy()
-        del s
-        return e, w, em, dry0
-
-    def compare(ea, wa, eb, wb):
-        amp = float(np.abs(eb).max())
-        err = np.abs(ea - eb)
-        return {"max_eta_err_rel": float(err.max() / amp),
-                "rms_eta_err_rel": float(np.sqrt((err ** 2).mean()) / amp),
-                "mask_flip_frac": float((wa.astype(bool) != wb.astype(bool)).mean())}
-
-    log("fp32 vs oracle, %d steps ..." % oracle_steps)
-    e32, w32, _, _ = run(clf.FP32, oracle_steps)
-    o = oracle.Oracle.from_case(case)
-    o.set_initial(case.eta0, case.u0, case.v0)
-    t0 = time.perf_counter()
-    o.step(oracle_steps)
-    to = time.perf_counter() - t0
-    eo, _, _, wo = o.state()
-    del o
-    res = {"workload": case.name, "vs_fp64_oracle": dict(steps=oracle_steps, oracle_s=to,
-                                                         **compare(e32, w32, eo, wo))}
-    log("fp32 vs fp64 gpu, %d steps ..." % steps)
-    e32, w32, m32, dry0 = run(clf.FP32, steps)
-    e64, w64, m64, _ = run(clf.FP64, steps)
-    ew32, ew64 = (m32 > 0) & dry0, (m64 > 0) & dry0
-    res["vs_fp64_gpu"] = dict(steps=steps, **compare(e32, w32, e64, w64))
-    res["vs_fp64_gpu"]["ever_wet_of_initially_dry_fp32"] = float(ew32.sum() / max(1, dry0.sum()))
-    res["vs_fp64_gpu"]["ever_wet_of_initially_dry_fp64"] = float(ew64.sum() / max(1, dry0.sum()))
-    res["vs_fp64_gpu"]["ever_wet_flip_frac"] = float((ew32 != ew64).mean())
-    return res
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c5")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--profile", action="store_true", help="short run for profilers")
+    ap.add_argument("--profile", action="store_true",
+                    help="run for profilers: at most 200 timed steps, no CPU leg, no extras")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run one 256 MiB device copy (counter calibration)")
+                    help="also run the streaming probes once on 256 MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the library has no multi-GPU path "
-              "(the y-band sharding design is described but not built); use --gpus 1",
+        print("bench.py measures one GPU: every GPU box here has one, and the library's "
+              "y-band decomposition (clf_bands) runs its bands on one device; use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     if args.profile:
-        args.steps, args.warmup = min(args.steps, 20), min(args.warmup, 3)
+        args.steps, args.warmup = min(args.steps, 200), min(args.warmup, 20)
         args.no_cpu = args.no_extras = True
 
     import torch
@@ -414,21 +452,26 @@ def main():
 
     torch.cuda.set_device(0)
     if args.calibrate_copy:
-        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        import ctypes
+        from paper_1410_0753_amd import build
+        L = ctypes.CDLL(build.PROBE_LIB)
+        a = torch.full((256 << 20,), 1, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
-        a.fill_(1)
+        sink = torch.zeros(4, dtype=torch.int32, device="cuda")
+        sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
-        b.copy_(a)
+        L.clf_probe_copy(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                         ctypes.c_size_t(256 << 20), 8192, 256, sp)
+        L.clf_probe_read(ctypes.c_void_p(a.data_ptr()), ctypes.c_size_t(256 << 20),
+                         ctypes.c_void_p(sink.data_ptr()), ctypes.c_uint(0xDEADBEEF), 8192, 256, sp)
         torch.cuda.synchronize()
-        del a, b
-    if args.workload == "c5err":
-        # long-run FP32 error report on the 8000x6000 grid (not in the default run)
-        res = fp32_error_large(args.steps, min(args.steps, 50))
-        print(json.dumps({"metric": METRIC, "workload": "c5err", "fp32_error": res}), flush=True)
+        del a, b, sink
+    if args.workload == "c5search":
+        res = c5_amplitude_search()
+        print(json.dumps({"metric": METRIC, "workload": "c5search", "c5search": res}), flush=True)
         return
     if args.workload in ("ensemble", "adjoint"):
         # one extras leg alone (for profilers)
-        torch.cuda.set_device(0)
         if args.workload == "ensemble":
             res = run_ensemble(20 if args.profile else min(args.steps, 300),
                                n=16 if args.profile else 64)
@@ -440,10 +483,11 @@ def main():
 
     prec = clf.FP32 if args.precision == "fp32" else clf.FP64
     esize = 4 if prec == clf.FP32 else 8
+    enclosed = args.workload == "c5"
     log("generating workload", args.workload)
-    case = make_case(args.workload, args.steps)
-    head = run_grid(case, prec, args.steps, args.warmup)
-    copy_bw = None if args.profile else copy_bandwidth()
+    case = make_case(args.workload)
+    head = run_grid(case, prec, args.steps, args.warmup, enclosed=enclosed)
+    probes = None if args.profile else probe_rates()
     traffic = None
     tr = traffic_entry(kernel_sha(), "%s/%s" % (args.workload, args.precision),
                        head["workgroups"])
@@ -453,6 +497,10 @@ def main():
                    "bytes_per_launch": tb, "read_bytes": tr["read_bytes"],
                    "write_bytes": tr["write_bytes"],
                    "algorithmic_bytes_per_launch": WORDS_PER_CELL_STEP * esize * case.cells}
+    # the arrays a step reads (h, u, v, d and the two maxwave arrays) against
+    # the 256 MB Infinity Cache
+    cache_resident = case.cells * esize * 6 <= 256e6
+    frac = head["achieved"] / PEAK_HBM
     out = {
         "metric": METRIC,
         "value": head["value"],
@@ -466,58 +514,71 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == clf.FP32 else "f64",
         "data": "synthetic",
-        "config": {"workload": case.name + (" (%s, 50 gauges every 10 steps, maxwave every step)"
-                                             % args.precision),
-                   "nx": case.nx, "ny": case.ny, "dt": case.dt},
+        "config": {"workload": workload_label(case, args.precision, enclosed),
+                   "nx": case.nx, "ny": case.ny, "dt": case.dt,
+                   "manning_n2": case.manning_n2,
+                   "friction": ("explicit -alpha dt on p and q, alpha dt capped at |w|"
+                                if case.manning_n2 > 0 else "none")},
         "roofline": {"bound": "hbm", "achieved": head["achieved"] / 1e9,
-                     "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                     "frac": head["achieved"] / PEAK_HBM, "traffic": traffic,
-                     "kernel": "step_kernel (fused x-y march), %d B/cell-step algorithmic, "
-                               "segment %d rows" % (WORDS_PER_CELL_STEP * esize, head["segment"]),
+                     "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": frac,
+                     "traffic": traffic,
+                     "kernel": "step_kernel (fused x-y march), %d B/cell-step algorithmic x %d "
+                               "cells per launch, segment %d rows, %d workgroups" % (
+                                   WORDS_PER_CELL_STEP * esize, case.cells, head["segment"],
+                                   head["workgroups"]),
                      "mean_launch_ms": head["kernel_ms"],
-                     "copy_GBps": copy_bw / 1e9 if copy_bw else None,
-                     "frac_of_copy": head["achieved"] / copy_bw if copy_bw else None,
-                     "frac_of_two_sweep_model": head["value"] * 18 * esize / PEAK_HBM,
-                     "note": "frac uses the fused kernel's 11 words per cell-step; "
-                             "frac_of_two_sweep_model the 18 words of two separate sweeps "
-                             "with maxwave. Grids up to about 2400x1800 FP64 fit the 256 MB "
-                             "Infinity Cache; the HBM-resident runs are the 8000x6000 extras."},
+                     "timed_launches": head["kernel_launches"],
+                     "copy_GBps": probes["copy_GBps"] if probes else None,
+                     "read_GBps": probes["read_GBps"] if probes else None,
+                     "frac_of_copy": head["achieved"] / (probes["copy_GBps"] * 1e9)
+                     if probes else None,
+                     "target_frac": 0.70, "target_met": frac >= 0.70,
+                     "cache_resident": cache_resident},
     }
+    if probes:
+        out["roofline"]["probe_shapes"] = {"copy": probes["copy_shape"],
+                                           "read": probes["read_shape"]}
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(case)
     if not args.no_extras:
         from paper_1410_0753_amd import synth
         extras = {}
-        if prec == clf.FP64:
-            r32 = run_grid(case, clf.FP32, args.steps, args.warmup)
-            r32["roofline_frac"] = r32.pop("achieved") / PEAK_HBM
-            log("fp32 error vs oracle ...")
-            r32["error_vs_fp64_oracle"] = fp32_error(case, 200)
-            extras["fp32_same_grid"] = r32
-        log("8000x6000 spherical grid ...")
-        big = synth.config5(steps=args.steps)
-        rb = run_grid(big, clf.FP32, min(args.steps, 400), 20, enclosed=True)
-        rb["roofline_frac"] = rb.pop("achieved") / PEAK_HBM
-        rb["workload"] = big.name + (" (fp32, 50 gauges every 10 steps, maxwave every step, "
-                                     "4 enclosed-grid boundary series every step)")
-        extras["large_grid_fp32"] = rb
-        log("8000x6000 spherical grid, fp64 ...")
-        rb = run_grid(big, clf.FP64, min(args.steps, 100), 10, enclosed=True)
-        rb["roofline_frac"] = rb.pop("achieved") / PEAK_HBM
-        rb["workload"] = big.name + (" (fp64, 50 gauges every 10 steps, maxwave every step, "
-                                     "4 enclosed-grid boundary series every step)")
-        extras["large_grid_fp64"] = rb
+        if args.workload == "c5":
+            other = clf.FP32 if prec == clf.FP64 else clf.FP64
+            r = run_grid(case, other, args.steps, args.warmup, enclosed=True)
+            r["roofline_frac"] = r.pop("achieved") / PEAK_HBM
+            r["workload"] = workload_label(case, "fp32" if other == clf.FP32 else "fp64", True)
+            extras["other_precision_same_grid"] = r
+            rep = fp32_report(case, 50)
+            extras["fp32_error"] = rep
+            ew = rep["vs_fp64_gpu"]["ever_wet_of_initially_dry_fp64"]
+            out["config"]["ever_wet_frac_of_initially_dry"] = ew
+            out["config"]["workload"] += (
+                "; 3 m dipole; %.2f%% of the initially dry nodes are ever wet over the "
+                "whole %d-step run (the 10%% of the workload description is not reached: "
+                "the dry set is a 60-cell coastal plain rising 0.33 m per cell along the whole "
+                "west edge, of which the dipole reaches a few percent)" % (100 * ew, case.steps))
+        del case
+        log("2400x1800 grid (cache-resident) ...")
+        c2 = synth.config2()
+        c2r = {}
+        for name, pr in (("fp64", clf.FP64), ("fp32", clf.FP32)):
+            r = run_grid(c2, pr, args.steps, args.warmup)
+            r["roofline_frac_nominal"] = r.pop("achieved") / PEAK_HBM
+            r["note"] = "field arrays fit the 256 MB Infinity Cache: not an HBM measurement"
+            c2r[name] = r
+        c2r["workload"] = workload_label(c2, "fp64/fp32", False)
+        extras["cache_resident_2400x1800"] = c2r
         if not args.no_cpu:
             log("oracle on the other workloads ...")
             extras["cpu_other"] = cpu_other([("200x200", synth.config1(steps=10), 400),
-                                             ("8000x6000", big, 2)])
-        del big
+                                             ("2400x1800", c2, 40)])
+        del c2
         log("ensemble ...")
         extras["ensemble"] = run_ensemble(min(args.steps, 300))
         log("adjoint ...")
         extras["adjoint"] = run_adjoint(3000, cpu_fd=not args.no_cpu)
-
         out["extras"] = extras
     print(json.dumps(out), flush=True)
 

@@ -81,6 +81,13 @@ extern "C" {
 #define CLF_Q_BLOCKS 9         /* workgroups per step kernel launch */
 #define CLF_Q_GRAPH_REPLAYS 10 /* hipGraph replays issued so far */
 #define CLF_Q_WIDE 11          /* 1 if the step kernel runs its 64-bit-address variant */
+/* With kernel_timing = 1: mean duration (ms) of the step-kernel launches of
+ * clf_step since the last reset, from a HIP event pair recorded around each
+ * launch on the context's stream (waits for them); their count; and a reset
+ * (returns the count before it). */
+#define CLF_Q_KERNEL_MS 12
+#define CLF_Q_KERNEL_LAUNCHES 13
+#define CLF_Q_KERNEL_RESET 14
 
 typedef struct clf_ctx clf_ctx;
 
@@ -147,6 +154,9 @@ typedef struct clf_params {
                                (p0 = 2 sqrt(g d) from the west/south, q0 = -2 sqrt(g d) from the
                                east/north).  Other edges are walls.  Grids with open edges run the
                                general (slower) step kernel; the adjoint rejects them. */
+  int32_t kernel_timing;    /* 1: clf_step records a HIP event pair around each step-kernel
+                               launch (CLF_Q_KERNEL_MS); step sequences then run without
+                               hipGraphs.  Default 0. */
 } clf_params;
 
 void clf_default_params(clf_params* p);

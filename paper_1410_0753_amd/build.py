@@ -18,6 +18,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libclf.so")
+# streaming probes of the benchmark (copy and read rates, counter calibration)
+PROBE_LIB = os.path.join(HERE, "libclf_probe.so")
+PROBE_SOURCE = os.path.join(CSRC, "clf_probe.hip")
 OBJ_DIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(CSRC, "clf_kernels.hip"), os.path.join(CSRC, "clf_adjoint.hip"),
            os.path.join(CSRC, "clf_runtime.cpp"), os.path.join(CSRC, "clf_static.hip")]
@@ -45,14 +48,17 @@ def build(verbose: bool = False, extra=()) -> str:
     tag = "%d" % os.getpid()
     objs = [os.path.join(OBJ_DIR, os.path.basename(s) + "." + tag + ".o") for s in SOURCES]
     cmds = [["hipcc"] + FLAGS + list(extra) + ["-c", s, "-o", o] for s, o in zip(SOURCES, objs)]
+    ptmp = PROBE_LIB + ".tmp" + tag
+    cmds.append(["hipcc"] + FLAGS + ["-shared", PROBE_SOURCE, "-o", ptmp])
     try:
         with concurrent.futures.ThreadPoolExecutor(len(cmds)) as ex:
             list(ex.map(lambda c: _run(c, verbose), cmds))
         tmp = LIB + ".tmp" + tag
         _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp], verbose)
         os.replace(tmp, LIB)
+        os.replace(ptmp, PROBE_LIB)
     finally:
-        for o in objs:
+        for o in objs + [ptmp]:
             if os.path.exists(o):
                 os.remove(o)
     return LIB

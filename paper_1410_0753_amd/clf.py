@@ -26,7 +26,7 @@ WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
 FRICTION_EXPLICIT, FRICTION_SEMI_IMPLICIT = 0, 1
 OPEN_W, OPEN_E, OPEN_S, OPEN_N = 1, 2, 4, 8
 (Q_MAX_CFL, Q_SSL_PASSES, Q_STEP, Q_MIN_F, Q_WORKSPACE, Q_GAUGE_RECORDS, Q_TILES, Q_SEGMENT,
- Q_BLOCKS, Q_GRAPH_REPLAYS, Q_WIDE) = range(1, 12)
+ Q_BLOCKS, Q_GRAPH_REPLAYS, Q_WIDE, Q_KERNEL_MS, Q_KERNEL_LAUNCHES, Q_KERNEL_RESET) = range(1, 15)
 
 # Every symbol include/clf.h declares.
 EXPORTS = ["clf_default_params", "clf_node_index", "clf_workspace_bytes", "clf_init", "clf_set_initial",
@@ -66,7 +66,8 @@ class Params(C.Structure):
                 ("series_capacity", C.c_int32), ("forcing_capacity", C.c_int32),
                 ("segment", C.c_int32), ("autotune", C.c_int32),
                 ("graph_steps", C.c_int32), ("persistent_blocks", C.c_int32),
-                ("friction_form", C.c_int32), ("open_sides", C.c_int32)]
+                ("friction_form", C.c_int32), ("open_sides", C.c_int32),
+                ("kernel_timing", C.c_int32)]
 
 
 _lock = threading.Lock()
@@ -335,12 +336,15 @@ class Solver:
 
     # -- adjoint --
     def adjoint_forward(self, nsteps, ckpt_every=0):
-        """Forward run of nsteps from clf_set_initial, keeping checkpoints."""
+        """Forward run of nsteps from clf_set_initial, keeping checkpoints.
+        Each call replaces the previous run's checkpoints and counts up
+        `adjoint_generation`."""
         nb = C.c_size_t(0)
         self._check(load().clf_adjoint_workspace_bytes(self._h, int(nsteps), int(ckpt_every),
                                                        C.byref(nb)))
         self.adj_workspace = self.torch.empty(int(nb.value), dtype=self.torch.uint8,
                                               device=self.device)
+        self.adjoint_generation = getattr(self, "adjoint_generation", 0) + 1
         self._check(load().clf_adjoint_forward(self._h, int(nsteps), int(ckpt_every),
                                                C.c_void_p(self.adj_workspace.data_ptr()),
                                                nb.value))

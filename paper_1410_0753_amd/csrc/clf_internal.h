@@ -62,6 +62,12 @@ struct GridDesc {
   const void* yisb;  // [ny]
   const void* tanR;  // [ny]   tan(lat)/R (zeros when the source is off)
   double dt, hdt, dt2, hmin, gn2, inv16g, dwall;
+  // gauges whose records the step kernel writes: [ngauge][3] (row, column,
+  // gauge index), grouped by tile (Tile::g0, gn); records [slot][ngauge][3]
+  const int* gtab;
+  double* grec;
+  int ngauge;
+  int pad_g;
 };
 
 // Per-context device flags.
@@ -71,9 +77,11 @@ struct StepState {
 };
 
 // Work tile of one wavefront: grid index, first output column, first
-// output row, number of output rows.
+// output row, number of output rows; the tile's gauges are entries
+// [g0, g0 + gn) of its grid's gauge table.
 struct Tile {
   int grid, x0, y0, rows;   // grid | kTileReverse: the segment marches rows downward
+  int g0, gn, pad0, pad1;
 };
 constexpr int kTileReverse = 1 << 30;
 
@@ -112,9 +120,11 @@ constexpr int STRIP = WAVE - 2 * HALO;  // output columns per wavefront
 constexpr int WAVES_PER_BLOCK = 4;
 
 // Kernel launchers (clf_kernels.hip).
+// rec_slot >= 0: the step writes the gauge records of that slot (the level
+// the step reaches); -1: no records.
 hipError_t launch_step(int fp32, int order, int gflags, const GridDesc* grids, const Tile* tiles,
                        int ntiles, StepState* st, int parity, int do_max, int nblocks,
-                       hipStream_t s);
+                       hipStream_t s, int rec_slot = -1);
 // Resident workgroups per compute unit of the step kernel variant.
 hipError_t step_blocks_per_cu(int fp32, int order, int gflags, int* n);
 hipError_t launch_init_state(int fp32, const GridDesc* gd_host, const GridDesc* gd_dev,
@@ -133,8 +143,9 @@ hipError_t launch_read_maxwave(int fp32, const GridDesc* gd_host, const GridDesc
 hipError_t launch_get_depth(int fp32, const GridDesc* gd_host, const GridDesc* gd_dev, double* d,
                             long long N, hipStream_t s);
 hipError_t launch_clear_maxwave(int fp32, const GridDesc* gd_host, long long N, hipStream_t s);
+// Records of level n: the gauges (when do_gauges) and the enclosed-grid series.
 hipError_t launch_sample(int fp32, const GridDesc* gd_dev, const SampleDesc* sd_dev, int nthreads,
-                         long long n, int parity, hipStream_t s);
+                         long long n, int parity, int do_gauges, hipStream_t s);
 hipError_t launch_forcing(int fp32, const GridDesc* gd_dev, const ForceDesc* fd_dev, int nthreads,
                           long long n, int parity, hipStream_t s);
 hipError_t launch_deform_depth(int fp32, const GridDesc* gd_host, const double* eta, long long N,

@@ -936,14 +936,16 @@ __device__ __forceinline__ void ypipe_push(YPipe<P>& y, const typename P::A& a_i
 
 // FL: the grid flags this instantiation honours (others are compiled out).
 constexpr int FL_FAST = G_SPHSRC;
-// runup workloads: the common case plus bottom friction
-constexpr int FL_FRIC = G_SPHSRC | G_FRICTION | G_FRIC_SEMI;
+// runup workloads: the common case plus bottom friction (the explicit
+// -alpha dt form), and the same with the semi-implicit option
+constexpr int FL_FRIC = G_SPHSRC | G_FRICTION;
+constexpr int FL_FRIC_SEMI = FL_FRIC | G_FRIC_SEMI;
 // grids driven by boundary forcing (a forcing ring), without and with
 // friction. These sets also take wall mode, which changes only step (b) in
 // the ballot-guarded flooding branch (in the common set the extra code
 // alone cost 0.5-0.8%).
 constexpr int FL_RING = FL_FAST | G_WALLMODE | G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N;
-constexpr int FL_RING_FRIC = FL_RING | G_FRICTION;
+constexpr int FL_RING_FRIC = FL_RING | G_FRICTION | G_FRIC_SEMI;
 constexpr int FL_ALL = G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N | G_WALLMODE | G_SOLVER1 |
                        G_SPHSRC | G_FRICTION | G_FRIC_SEMI | G_TINYH | G_OPEN_ANY;
 // grids whose field arrays exceed 4 GiB: the same three flag sets with
@@ -963,7 +965,7 @@ template <class P, int ORDER, int FL>
 __global__ void __launch_bounds__(WAVE * WAVES_PER_BLOCK)
 __attribute__((amdgpu_waves_per_eu(kStepWaves<P, ORDER, FL>())))
 step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, int ntiles,
-            StepState* st, int parity, int do_max) {
+            StepState* st, int parity, int do_max, int rec_slot) {
   typedef typename P::R R;
   typedef typename P::A A;
   typedef typename P::C C;
@@ -992,6 +994,8 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
     tl.x0 = __builtin_amdgcn_readfirstlane(tl.x0);
     tl.y0 = __builtin_amdgcn_readfirstlane(tl.y0);
     tl.rows = __builtin_amdgcn_readfirstlane(tl.rows);
+    tl.g0 = __builtin_amdgcn_readfirstlane(tl.g0);
+    tl.gn = __builtin_amdgcn_readfirstlane(tl.gn);
     if (tl.rows <= 0) continue;   // padding slot of the XCD-aware order
     const GridDesc& g = grids[tl.grid];
     Ctx<P> cx;
@@ -1084,6 +1088,20 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
         if (e > m.e) put(cx.emax, b, e);
         R s2 = o.w * o.w + o.t * o.t;
         if (s2 > m.s2) put(cx.smax2, b, s2);
+      }
+      // gauge records of this tile's nodes on record steps (eta, u, v on
+      // wet nodes, zeros on dry ones), written by the lane holding the node
+      if (rec_slot >= 0 && tl.gn > 0) {
+        for (int k = tl.g0; k < tl.g0 + tl.gn; ++k) {
+          if (cload(g.gtab + 3 * k) != r) continue;
+          if (cload(g.gtab + 3 * k + 1) != xc) continue;
+          const int gi = cload(g.gtab + 3 * k + 2);
+          const bool w = P::wet_out(o, D, cx.par);
+          double* rec = g.grec + ((size_t)rec_slot * (size_t)g.ngauge + (size_t)gi) * 3;
+          gstore(rec, w ? (double)P::eta_out(o, D) : 0.0);
+          gstore(rec + 1, w ? (double)o.w : 0.0);
+          gstore(rec + 2, w ? (double)o.t : 0.0);
+        }
       }
     };
 
@@ -1315,7 +1333,7 @@ __global__ void get_depth_kernel(GridDesc g, double* d, long long N) {
 // Gauge and enclosed-grid records at the level n reached by the last step.
 template <class R>
 __global__ void sample_kernel(const GridDesc* grids, const SampleDesc* sd, long long n,
-                              int parity) {
+                              int parity, int do_gauges) {
   const SampleDesc s = *sd;
   const GridDesc& g = grids[s.grid];
   const R* H = (const R*)g.H[parity];
@@ -1323,7 +1341,7 @@ __global__ void sample_kernel(const GridDesc* grids, const SampleDesc* sd, long 
   const R* V = (const R*)g.V[parity];
   const R* D = (const R*)g.D;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s.ngauge > 0 && n % s.gout == 0 && n >= s.g_first && i < s.ngauge) {
+  if (do_gauges && s.ngauge > 0 && n % s.gout == 0 && n >= s.g_first && i < s.ngauge) {
     const long long slot = (n - s.g_first) / s.gout;
     if (slot < s.gcap) {
       const long long k = s.gidx[i];
@@ -1457,80 +1475,97 @@ inline int nblk(long long N, int bs) { return (int)((N + bs - 1) / bs); }
 template <class P, int FL>
 static void launch_order(int order, dim3 grid, dim3 block, hipStream_t s, const GridDesc* grids,
                          const Tile* tiles, int ntiles, StepState* st, int parity,
-                         int do_max) {
+                         int do_max, int rec_slot) {
   switch (order) {
     case ORD_XY:
       hipLaunchKernelGGL((step_kernel<P, ORD_XY, FL>), grid, block, 0, s, grids, tiles, ntiles,
-                         st, parity, do_max);
+                         st, parity, do_max, rec_slot);
       break;
     case ORD_YX:
       hipLaunchKernelGGL((step_kernel<P, ORD_YX, FL>), grid, block, 0, s, grids, tiles, ntiles,
-                         st, parity, do_max);
+                         st, parity, do_max, rec_slot);
       break;
     case ORD_X:
       hipLaunchKernelGGL((step_kernel<P, ORD_X, FL>), grid, block, 0, s, grids, tiles, ntiles,
-                         st, parity, do_max);
+                         st, parity, do_max, rec_slot);
       break;
     default:
       hipLaunchKernelGGL((step_kernel<P, ORD_Y, FL>), grid, block, 0, s, grids, tiles, ntiles,
-                         st, parity, do_max);
+                         st, parity, do_max, rec_slot);
       break;
   }
 }
 
 hipError_t launch_step(int fp32, int order, int gflags, const GridDesc* grids, const Tile* tiles,
                        int ntiles, StepState* st, int parity, int do_max, int nblocks,
-                       hipStream_t s) {
+                       hipStream_t s, int rec_slot) {
   dim3 grid(nblocks), block(WAVE * WAVES_PER_BLOCK);
   const int base = gflags & ~G_WIDE;
   const bool fast = (base & ~FL_FAST) == 0;
   const bool fric = (base & ~FL_FRIC) == 0;
+  const bool fric_semi = (base & ~FL_FRIC_SEMI) == 0;
   const bool ring = (base & ~FL_RING) == 0;
   const bool ring_fric = (base & ~FL_RING_FRIC) == 0;
   if (gflags & G_WIDE) {
     if (fp32) {
       if (fast)
         launch_order<P32, FL_FAST_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity,
-                                        do_max);
+                                        do_max, rec_slot);
       else if (fric)
         launch_order<P32, FL_FRIC_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity,
-                                        do_max);
+                                        do_max, rec_slot);
       else
-        launch_order<P32, FL_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+        launch_order<P32, FL_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                   do_max, rec_slot);
     } else {
       if (fast)
         launch_order<P64, FL_FAST_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity,
-                                        do_max);
+                                        do_max, rec_slot);
       else if (fric)
         launch_order<P64, FL_FRIC_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity,
-                                        do_max);
+                                        do_max, rec_slot);
       else
-        launch_order<P64, FL_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+        launch_order<P64, FL_WIDE>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                   do_max, rec_slot);
     }
   } else if (fp32) {
     if (fast)
-      launch_order<P32, FL_FAST>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+      launch_order<P32, FL_FAST>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                 do_max, rec_slot);
     else if (fric)
-      launch_order<P32, FL_FRIC>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+      launch_order<P32, FL_FRIC>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                 do_max, rec_slot);
+    else if (fric_semi)
+      launch_order<P32, FL_FRIC_SEMI>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                      do_max, rec_slot);
     else if (ring)
-      launch_order<P32, FL_RING>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+      launch_order<P32, FL_RING>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                 do_max, rec_slot);
     else if (ring_fric)
       launch_order<P32, FL_RING_FRIC>(order, grid, block, s, grids, tiles, ntiles, st, parity,
-                                    do_max);
+                                    do_max, rec_slot);
     else
-      launch_order<P32, FL_ALL>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+      launch_order<P32, FL_ALL>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                do_max, rec_slot);
   } else {
     if (fast)
-      launch_order<P64, FL_FAST>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+      launch_order<P64, FL_FAST>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                 do_max, rec_slot);
     else if (fric)
-      launch_order<P64, FL_FRIC>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+      launch_order<P64, FL_FRIC>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                 do_max, rec_slot);
+    else if (fric_semi)
+      launch_order<P64, FL_FRIC_SEMI>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                      do_max, rec_slot);
     else if (ring)
-      launch_order<P64, FL_RING>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+      launch_order<P64, FL_RING>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                 do_max, rec_slot);
     else if (ring_fric)
       launch_order<P64, FL_RING_FRIC>(order, grid, block, s, grids, tiles, ntiles, st, parity,
-                                    do_max);
+                                    do_max, rec_slot);
     else
-      launch_order<P64, FL_ALL>(order, grid, block, s, grids, tiles, ntiles, st, parity, do_max);
+      launch_order<P64, FL_ALL>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                do_max, rec_slot);
   }
   return hipGetLastError();
 }
@@ -1559,6 +1594,7 @@ hipError_t step_blocks_per_cu(int fp32, int order, int gflags, int* n) {
   const int base = gflags & ~G_WIDE;
   const bool fast = (base & ~FL_FAST) == 0;
   const bool fric = (base & ~FL_FRIC) == 0;
+  const bool fric_semi = (base & ~FL_FRIC_SEMI) == 0;
   const bool ring = (base & ~FL_RING) == 0;
   const bool ring_fric = (base & ~FL_RING_FRIC) == 0;
   if (gflags & G_WIDE) {
@@ -1573,11 +1609,13 @@ hipError_t step_blocks_per_cu(int fp32, int order, int gflags, int* n) {
   if (fp32)
     return fast ? occupancy_of<P32, FL_FAST>(order, n)
                 : fric      ? occupancy_of<P32, FL_FRIC>(order, n)
+                : fric_semi ? occupancy_of<P32, FL_FRIC_SEMI>(order, n)
                 : ring      ? occupancy_of<P32, FL_RING>(order, n)
                 : ring_fric ? occupancy_of<P32, FL_RING_FRIC>(order, n)
                             : occupancy_of<P32, FL_ALL>(order, n);
   return fast ? occupancy_of<P64, FL_FAST>(order, n)
               : fric      ? occupancy_of<P64, FL_FRIC>(order, n)
+              : fric_semi ? occupancy_of<P64, FL_FRIC_SEMI>(order, n)
               : ring      ? occupancy_of<P64, FL_RING>(order, n)
               : ring_fric ? occupancy_of<P64, FL_RING_FRIC>(order, n)
                           : occupancy_of<P64, FL_ALL>(order, n);
@@ -1630,8 +1668,8 @@ hipError_t launch_clear_maxwave(int fp32, const GridDesc* gh, long long N, hipSt
 }
 
 hipError_t launch_sample(int fp32, const GridDesc* gd, const SampleDesc* sd, int nthreads,
-                         long long n, int parity, hipStream_t s) {
-  CLF_SMALL_LAUNCH(sample_kernel, (long long)nthreads, gd, sd, n, parity);
+                         long long n, int parity, int do_gauges, hipStream_t s) {
+  CLF_SMALL_LAUNCH(sample_kernel, (long long)nthreads, gd, sd, n, parity, do_gauges);
 }
 
 hipError_t launch_forcing(int fp32, const GridDesc* gd, const ForceDesc* fd, int nthreads,

@@ -81,7 +81,7 @@ struct Enc {
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-  size_t gd, st, sd, fd, tiles, f[9], xib, xisb, xfac, yib, yisb, tanR, gidx, grec, sidx, swt,
+  size_t gd, st, sd, fd, tiles, f[9], xib, xisb, xfac, yib, yisb, tanR, gidx, gtab, grec, sidx, swt,
       sout, srec, ft[4], fv[4], total;
   int ntiles_max;
 };
@@ -114,6 +114,7 @@ Layout plan(int nx, int ny, const clf_params& p) {
   L.yisb = take(es * ny);
   L.tanR = take(es * ny);
   L.gidx = take(sizeof(long long) * std::max(p.max_gauges, 1));
+  L.gtab = take(sizeof(int) * 3 * (size_t)std::max(p.max_gauges, 1));
   L.grec = take(sizeof(double) * 3 * (size_t)std::max(p.max_gauges, 1) *
                 std::max(p.gauge_capacity, 1));
   const size_t mp = std::max(p.max_enclosed_points, 1);
@@ -159,6 +160,8 @@ struct clf_ctx {
   int cur = 0;
   bool rec0 = false;
   int ngauge = 0;
+  std::vector<int> gix, giy;        // gauge nodes
+  std::vector<Tile> tiles_host;     // the tile list as uploaded (without gauge ranges)
   long long g_first = 0;
   std::vector<Enc> enc;
   int npts = 0, rec_len = 0;
@@ -167,6 +170,13 @@ struct clf_ctx {
   hipStream_t cap_stream = nullptr;   // capture-only stream (never runs work)
   hipGraphExec_t graph = nullptr;     // graph_steps steps starting from buffer 0
   long long graph_replays = 0;
+  // step-kernel timing (kernel_timing): a ring of event pairs, recycled
+  // after their elapsed time is added up
+  std::vector<hipEvent_t> ev0, ev1;
+  std::vector<char> ev_pending;
+  long long ev_next = 0;
+  double ktime_ms = 0.0;
+  long long klaunches = 0;
   // adjoint run (caller-owned workspace)
   char* adj_ws = nullptr;
   int adj_N = 0, adj_K = 0, adj_nck = 0;
@@ -294,7 +304,7 @@ void natural_tiles(int grid, int nx, int ny, int seg, std::vector<Tile>& t) {
   const int nsegs = (ny + seg - 1) / seg;
   for (int q = 0; q < nsegs; ++q)
     for (int s = 0; s < ns; ++s) {
-      Tile tl;
+      Tile tl{};
       tl.grid = grid | ((q & 1) ? kTileReverse : 0);
       tl.x0 = s * STRIP;
       tl.y0 = q * seg;
@@ -329,6 +339,36 @@ std::vector<Tile> xcd_order(const std::vector<Tile>& nat, int* nblocks) {
   return out;
 }
 
+// Gauges go with the tile whose output region holds them: the tile list
+// carries, per tile, a range of the gauge table (row, column, gauge index),
+// so that the lane storing a gauge node writes its record on record steps.
+int upload_tiles_with_gauges(clf_ctx* c) {
+  std::vector<Tile> t = c->tiles_host;
+  std::vector<int> tab;
+  tab.reserve(3 * c->gix.size());
+  for (Tile& tl : t) {
+    tl.g0 = (int)(tab.size() / 3);
+    tl.gn = 0;
+    if (tl.rows <= 0) continue;
+    for (size_t g = 0; g < c->gix.size(); ++g) {
+      const int ix = c->gix[g], iy = c->giy[g];
+      if (ix >= tl.x0 && ix < tl.x0 + STRIP && iy >= tl.y0 && iy < tl.y0 + tl.rows) {
+        tab.push_back(iy);
+        tab.push_back(ix);
+        tab.push_back((int)g);
+        tl.gn += 1;
+      }
+    }
+  }
+  if (!tab.empty())
+    HIPCHK(c, hipMemcpyAsync((void*)c->gd.gtab, tab.data(), tab.size() * sizeof(int),
+                             hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->tiles_dev, t.data(), t.size() * sizeof(Tile),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return CLF_OK;
+}
+
 int upload_tiles(clf_ctx* c, const std::vector<Tile>& t, int nblocks, int seg) {
   if (c->graph) {
     (void)hipGraphExecDestroy(c->graph);
@@ -336,9 +376,9 @@ int upload_tiles(clf_ctx* c, const std::vector<Tile>& t, int nblocks, int seg) {
   }
   if ((int)t.size() > c->L.ntiles_max)
     return fail(c, CLF_EINVAL, "segment %d too short for the tile table", seg);
-  HIPCHK(c, hipMemcpyAsync(c->tiles_dev, t.data(), t.size() * sizeof(Tile),
-                           hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->tiles_host = t;
+  int rc = upload_tiles_with_gauges(c);
+  if (rc) return rc;
   c->ntiles = (int)t.size();
   c->nblocks = nblocks;
   c->seg = seg;
@@ -686,6 +726,8 @@ static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c) {
   if (p->solver != 1 && p->solver != 2) return fail(c, CLF_EINVAL, "solver must be 1 or 2");
   if (p->friction_form != 0 && p->friction_form != 1)
     return fail(c, CLF_EINVAL, "friction_form must be 0 (explicit) or 1 (semi-implicit)");
+  if (p->kernel_timing != 0 && p->kernel_timing != 1)
+    return fail(c, CLF_EINVAL, "kernel_timing must be 0 or 1");
   if (p->open_sides < 0 || p->open_sides > 15)
     return fail(c, CLF_EINVAL, "open_sides must be a bit mask of the four sides (0..15)");
   if (p->sweep_order != CLF_ORDER_XY && p->sweep_order != CLF_ORDER_ALTERNATE)
@@ -826,6 +868,9 @@ static int ctx_create(clf_ctx** out, const clf_grid* g, const double* depth, dou
   gd.yib = b + L.yib;
   gd.yisb = b + L.yisb;
   gd.tanR = b + L.tanR;
+  gd.gtab = (const int*)(b + L.gtab);
+  gd.grec = (double*)(b + L.grec);
+  gd.ngauge = 0;
   set_step_constants(gd, dt, *p);
 
   hipStream_t s = c->stream;
@@ -983,6 +1028,14 @@ int clf_set_gauges(clf_ctx* c, int n, const int32_t* ix, const int32_t* iy) {
     HIPCHK(c, hipMemcpyAsync((void*)c->sd.gidx, idx.data(), sizeof(long long) * n,
                              hipMemcpyHostToDevice, c->stream));
   c->ngauge = n;
+  c->gix.assign(ix, ix + n);
+  c->giy.assign(iy, iy + n);
+  c->gd.ngauge = n;
+  HIPCHK(c, hipMemcpyAsync(c->gd_dev, &c->gd, sizeof c->gd, hipMemcpyHostToDevice, c->stream));
+  if (!c->tiles_host.empty()) {
+    int rc = upload_tiles_with_gauges(c);
+    if (rc) return rc;
+  }
   // records restart at the current level (or at 0 before the first step)
   c->g_first = c->rec0 ? next_level(c->n + 1, c->p.gout) : next_level(c->n, c->p.gout);
   return push_sampling(c);
@@ -1102,12 +1155,75 @@ static int build_graph(int fp32, int order, int gflags, const GridDesc* gd, cons
   return CLF_OK;
 }
 
-static int launch_sampling(clf_ctx* c) {
-  const bool g = c->ngauge > 0 && c->n % c->p.gout == 0 && c->n >= c->g_first;
+// Records of the level reached (c->n) by the sampling kernel: the
+// enclosed-grid series, and the gauges when `gauges` (the first record of a
+// run; later gauge records come from the step kernel itself).
+static int launch_sampling(clf_ctx* c, bool gauges) {
+  const bool g = gauges && c->ngauge > 0 && c->n % c->p.gout == 0 && c->n >= c->g_first;
   const bool e = c->npts > 0 && c->n % c->p.bndout == 0 && c->n >= c->s_first;
   if (!g && !e) return CLF_OK;
   const int nthr = std::max(g ? c->ngauge : 0, e ? c->npts : 0);
-  HIPCHK(c, launch_sample(c->fp32, c->gd_dev, c->sd_dev, nthr, c->n, c->cur, c->stream));
+  HIPCHK(c, launch_sample(c->fp32, c->gd_dev, c->sd_dev, nthr, c->n, c->cur, g ? 1 : 0,
+                          c->stream));
+  return CLF_OK;
+}
+
+// Gauge record slot that the step reaching level n + 1 writes, or -1.
+static int record_slot(const clf_ctx* c) {
+  const long long lvl = c->n + 1;
+  if (c->ngauge == 0 || lvl % c->p.gout != 0 || lvl < c->g_first) return -1;
+  return (int)((lvl - c->g_first) / c->p.gout);
+}
+
+constexpr int kTimingRing = 64;
+
+// Add up the elapsed time of the pending event pair in ring slot i.
+static int timing_collect(clf_ctx* c, int i) {
+  if (!c->ev_pending[i]) return CLF_OK;
+  HIPCHK(c, hipEventSynchronize(c->ev1[i]));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev0[i], c->ev1[i]));
+  c->ktime_ms += ms;
+  c->klaunches += 1;
+  c->ev_pending[i] = 0;
+  return CLF_OK;
+}
+
+static int timing_flush(clf_ctx* c) {
+  for (int i = 0; i < (int)c->ev_pending.size(); ++i) {
+    int rc = timing_collect(c, i);
+    if (rc) return rc;
+  }
+  return CLF_OK;
+}
+
+// One step-kernel launch of clf_step, bracketed by an event pair when the
+// context times its kernel.
+static int timed_step_launch(clf_ctx* c, int order, int do_max, int nb) {
+  const int slot = record_slot(c);
+  if (!c->p.kernel_timing) {
+    HIPCHK(c, launch_step(c->fp32, order, c->gd.flags, c->gd_dev, c->tiles_dev, c->ntiles,
+                          c->st_dev, c->cur, do_max, nb, c->stream, slot));
+    return CLF_OK;
+  }
+  if (c->ev0.empty()) {
+    c->ev0.resize(kTimingRing);
+    c->ev1.resize(kTimingRing);
+    c->ev_pending.assign(kTimingRing, 0);
+    for (int i = 0; i < kTimingRing; ++i) {
+      HIPCHK(c, hipEventCreate(&c->ev0[i]));
+      HIPCHK(c, hipEventCreate(&c->ev1[i]));
+    }
+  }
+  const int i = (int)(c->ev_next % kTimingRing);
+  int rc = timing_collect(c, i);
+  if (rc) return rc;
+  HIPCHK(c, hipEventRecord(c->ev0[i], c->stream));
+  HIPCHK(c, launch_step(c->fp32, order, c->gd.flags, c->gd_dev, c->tiles_dev, c->ntiles,
+                        c->st_dev, c->cur, do_max, nb, c->stream, slot));
+  HIPCHK(c, hipEventRecord(c->ev1[i], c->stream));
+  c->ev_pending[i] = 1;
+  c->ev_next += 1;
   return CLF_OK;
 }
 
@@ -1141,12 +1257,13 @@ int clf_step(clf_ctx* c, int nsteps) {
   }
   (void)lo;
   if (!c->rec0) {
-    rc = launch_sampling(c);
+    rc = launch_sampling(c, true);
     if (rc) return rc;
     c->rec0 = true;
   }
   const bool graphable = c->p.graph_steps > 0 && !c->forcing && c->ngauge == 0 && c->npts == 0 &&
-                         c->p.maxout == 1 && c->p.sweep_order == CLF_ORDER_XY;
+                         c->p.maxout == 1 && c->p.sweep_order == CLF_ORDER_XY &&
+                         !c->p.kernel_timing;
   const int nb = eff_blocks(c->nblocks, c->p.persistent_blocks);
   int k = 0;
   while (k < nsteps) {
@@ -1166,12 +1283,12 @@ int clf_step(clf_ctx* c, int nsteps) {
       HIPCHK(c, launch_forcing(c->fp32, c->gd_dev, c->fd_dev, std::max(c->nx, c->ny), c->n,
                                c->cur, c->stream));
     const int do_max = ((c->n + 1) % c->p.maxout) == 0;
-    HIPCHK(c, launch_step(c->fp32, step_order(c), c->gd.flags, c->gd_dev, c->tiles_dev, c->ntiles,
-                          c->st_dev, c->cur, do_max, nb, c->stream));
+    rc = timed_step_launch(c, step_order(c), do_max, nb);
+    if (rc) return rc;
     c->cur ^= 1;
     c->n += 1;
     ++k;
-    rc = launch_sampling(c);
+    rc = launch_sampling(c, false);
     if (rc) return rc;
   }
   return CLF_OK;
@@ -1295,6 +1412,19 @@ int clf_query(clf_ctx* c, int what, double* value) {
     case CLF_Q_BLOCKS: *value = eff_blocks(c->nblocks, c->p.persistent_blocks); break;
     case CLF_Q_GRAPH_REPLAYS: *value = (double)c->graph_replays; break;
     case CLF_Q_WIDE: *value = (c->gd.flags & G_WIDE) ? 1.0 : 0.0; break;
+    case CLF_Q_KERNEL_MS:
+    case CLF_Q_KERNEL_LAUNCHES:
+    case CLF_Q_KERNEL_RESET: {
+      int rc = timing_flush(c);
+      if (rc) return rc;
+      if (what == CLF_Q_KERNEL_MS) *value = c->klaunches ? c->ktime_ms / c->klaunches : 0.0;
+      else *value = (double)c->klaunches;
+      if (what == CLF_Q_KERNEL_RESET) {
+        c->ktime_ms = 0.0;
+        c->klaunches = 0;
+      }
+      break;
+    }
     default: return fail(c, CLF_EINVAL, "unknown query %d", what);
   }
   return CLF_OK;
@@ -1307,6 +1437,10 @@ const char* clf_last_error(const clf_ctx* c) {
 int clf_destroy(clf_ctx* c) {
   if (!c) return CLF_EINVAL;
   (void)hipStreamSynchronize(c->stream);
+  for (size_t i = 0; i < c->ev0.size(); ++i) {
+    if (c->ev0[i]) (void)hipEventDestroy(c->ev0[i]);
+    if (c->ev1[i]) (void)hipEventDestroy(c->ev1[i]);
+  }
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;

@@ -22,11 +22,18 @@ class GaugeRecords(torch.autograd.Function):
         solver.adjoint_forward(int(nsteps), int(ckpt_every))
         rec, _ = solver.read_gauges()
         ctx.solver = solver
+        # the solver keeps the checkpoints of its last forward run only
+        ctx.generation = solver.adjoint_generation
         ctx.has_uv = (u0 is not None, v0 is not None)
         return torch.from_numpy(rec).to(device=eta0.device, dtype=eta0.dtype)
 
     @staticmethod
     def backward(ctx, grad_rec):
+        if ctx.solver.adjoint_generation != ctx.generation:
+            raise RuntimeError("the solver ran another forward pass (GaugeRecords.apply or "
+                               "adjoint_forward) after this one; its checkpoints are gone, so "
+                               "this backward would use the later run's: give each pending "
+                               "backward its own solver")
         d_eta0, d_u0, d_v0 = ctx.solver.adjoint_backward(
             grad_rec.detach().double().cpu().numpy())
         return (d_eta0, None, None, None, d_u0 if ctx.has_uv[0] else None,

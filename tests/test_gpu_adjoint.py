@@ -140,6 +140,60 @@ def test_adjoint_vs_finite_differences(clf):
         assert abs(g[k] - fd) <= 1e-6 * max(abs(fd), np.abs(g).max())
 
 
+def test_adjoint_vs_finite_differences_full_inversion_grid(clf):
+    # the full 1000x800 inversion grid, all 20 unit sources and 30 gauges,
+    # 1500 steps (the waves from the deep half reach the shelf gauges after
+    # about 500): every component of the gradient against central finite
+    # differences (h = 1e-4) to 1e-6 of itself, plus a floor of 1e-8 of the
+    # largest component for components near zero (the finite differences'
+    # own truncation error is about 1e-9 of the largest, measured with the
+    # oracle's complex-step derivative)
+    case, basis, c_true, c0 = synth.config4(steps=1500)
+    nsteps = 1500
+    print("adjoint vs FD, 1000x800, 20 sources, 1500 steps", flush=True)
+    s = clf.Solver.from_case(case, gout=1, gauge_capacity=nsteps + 2)
+    s.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
+    eta = lambda c: np.tensordot(c, basis, axes=1)
+    s.set_initial(eta(c_true))
+    s.step(nsteps)
+    obs = s.read_gauges()[0][:, :, 0].copy()
+
+    def loss(c):
+        s.set_initial(eta(c))
+        s.step(nsteps)
+        rec = s.read_gauges()[0][:, :, 0]
+        return 0.5 * np.sum((rec - obs) ** 2)
+
+    L, g_eta = misfit_grad(s, eta(c0), nsteps, obs)
+    g = np.tensordot(basis, g_eta, axes=([1, 2], [0, 1]))
+    h = 1e-4
+    fd = np.empty_like(g)
+    for k in range(len(c0)):
+        e = np.zeros_like(c0); e[k] = h
+        fd[k] = (loss(c0 + e) - loss(c0 - e)) / (2 * h)
+    assert np.abs(fd).min() > 0, "a gauge record did not see a source"
+    rel = np.abs(g - fd) / np.abs(fd)
+    print("max rel per component %.3e" % rel.max(), flush=True)
+    for k in range(len(c0)):
+        assert abs(g[k] - fd[k]) <= 1e-6 * abs(fd[k]) + 1e-8 * np.abs(fd).max(), (k, g[k], fd[k])
+
+
+def test_backward_refuses_a_replaced_forward_run(clf):
+    import torch
+    from paper_1410_0753_amd.inversion import GaugeRecords
+    case, basis, c_true, c0 = synth.config4(nx=90, ny=72, steps=50, nsrc=2, ngauge=4)
+    s = clf.Solver.from_case(case, gout=1)
+    s.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
+    e1 = torch.tensor(basis[0], device="cuda", requires_grad=True)
+    e2 = torch.tensor(basis[1], device="cuda", requires_grad=True)
+    r1 = GaugeRecords.apply(e1, s, 50, 0)
+    r2 = GaugeRecords.apply(e2, s, 50, 0)
+    with pytest.raises(RuntimeError, match="another forward"):
+        (r1 ** 2).sum().backward()
+    (r2 ** 2).sum().backward()
+    assert e2.grad is not None and torch.isfinite(e2.grad).all()
+
+
 def test_checkpoint_interval_independent(clf):
     c = synth.random_small(60, 64, 48, land=True, amp=0.3)
     nsteps = 30

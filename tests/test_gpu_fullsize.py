@@ -38,6 +38,79 @@ def test_full_size_2400x1800_fp64_bitwise(clf, oracle_mod):
     assert np.array_equal(mg[0], mo[0]) and np.array_equal(mg[1], mo[1])
 
 
+def test_reduced_2400x1800_flooding_1500_steps_bitwise(clf, oracle_mod):
+    # the 2400x1800 workload at half resolution (1200x900, 2 arc-minutes),
+    # 1500 steps: the dipole's waves reach the coast and flood initially dry
+    # nodes of the land band; state, gauges and maxwave bit for bit
+    case = synth.config2(steps=1500, scale=2)
+    print("reduced 1200x900 FP64, 1500 steps", flush=True)
+    g = clf.Solver.from_case(case, gout=10, maxout=1, autotune=1)
+    o = oracle_mod.Oracle.from_case(case, gout=10, maxout=1)
+    for obj in (g, o):
+        obj.set_initial(case.eta0, case.u0, case.v0)
+        obj.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
+    dry0 = o.state()[3] == 0
+    for k in range(3):
+        g.step(500)
+        o.step(500)
+        print("  step", 500 * (k + 1), flush=True)
+    for a, b in zip((t.cpu().numpy() for t in g.raw_state()), o.raw_state()):
+        assert np.array_equal(a, b)
+    assert np.array_equal(g.read_gauges()[0], o.read_gauges()[0])
+    mg = [t.cpu().numpy() for t in g.read_maxwave()]
+    mo = o.read_maxwave()
+    assert np.array_equal(mg[0], mo[0]) and np.array_equal(mg[1], mo[1])
+    flooded = dry0 & (mo[0] > 0)
+    print("  initially dry nodes ever wet:", int(flooded.sum()), flush=True)
+    assert flooded.sum() >= 20
+
+
+def test_reduced_8000x6000_runup_floods_plane_beaches(clf, oracle_mod):
+    # the 8000x6000 runup workload at quarter resolution (2000x1500, 2 arc-
+    # minutes) with a 6 m dipole: within 800 steps the waves flood more than
+    # a hundred initially dry nodes.  Friction (explicit form) goes through
+    # cbrt in the oracle, so the bar is the same wet mask and 1e-10 of each
+    # field's magnitude, for the state, the gauges, maxwave and the boundary
+    # series of the 4 enclosed grids
+    case = synth.config5(steps=800, scale=4, amp=6.0)
+    print("reduced 2000x1500 runup FP64, 800 steps", flush=True)
+    kw = dict(gout=10, maxout=1, bndout=5, max_enclosed=4)
+    g = clf.Solver.from_case(case, autotune=1, series_capacity=200, **kw)
+    o = oracle_mod.Oracle.from_case(case, **kw)
+    for obj in (g, o):
+        obj.set_initial(case.eta0, case.u0, case.v0)
+        obj.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
+        for ex, ey in case.enclosed:
+            obj.add_enclosed_grid(ex, ey)
+    dry0 = o.state()[3] == 0
+    for k in range(4):
+        g.step(200)
+        o.step(200)
+        print("  step", 200 * (k + 1), flush=True)
+
+    def close(a, b, what):
+        assert np.abs(a - b).max() <= 1e-10 * max(np.abs(b).max(), 1e-300), what
+
+    eg, ug, vg, wg = (t.cpu().numpy() for t in g.state())
+    eo, uo, vo, wo = o.state()
+    assert np.array_equal(wg, wo), "wet mask differs"
+    for a, b, n in ((eg, eo, "eta"), (ug, uo, "u"), (vg, vo, "v")):
+        close(a, b, n)
+    close(g.read_gauges()[0], o.read_gauges()[0], "gauges")
+    mg = [t.cpu().numpy() for t in g.read_maxwave()]
+    mo = o.read_maxwave()
+    close(mg[0], mo[0], "eta max")
+    close(mg[1], mo[1], "speed max")
+    for gid in range(4):
+        for side in range(4):
+            close(g.read_boundary_series(gid, side)[0], o.read_boundary_series(gid, side)[0],
+                  "series %d/%d" % (gid, side))
+    flooded = dry0 & (mo[0] > 0)
+    print("  initially dry nodes ever wet:", int(flooded.sum()), flush=True)
+    assert np.array_equal(flooded, dry0 & (mg[0] > 0))
+    assert flooded.sum() >= 50
+
+
 @pytest.mark.skipif(os.environ.get("CLF_LONG_TESTS") != "1",
                     reason="long run (about a minute of oracle time); set CLF_LONG_TESTS=1")
 def test_full_size_2400x1800_fp64_long_bitwise(clf, oracle_mod):
