@@ -66,13 +66,33 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1410_0753_amd", "csrc", "clf_kernels.hip"
 # shape; an entry applies only to a launch of the same workgroup count
 # (segment length), which the autotuner may choose differently run to run.
 TRAFFIC = {
-    "9c29862b1b599625c1c0a3659d6523945f28be11f0b9c419852ef46673b71221": {
-        "c2/fp64": [{"workgroups": 760, "read_bytes": 236000000, "write_bytes": 111200000}],
-        "c2/fp32": [{"workgroups": 1000, "read_bytes": 115900000, "write_bytes": 52700000}],
-        "c5/fp32": [{"workgroups": 4072, "read_bytes": 1314500000, "write_bytes": 604300000},
-                    {"workgroups": 4320, "read_bytes": 1324600000, "write_bytes": 601600000}],
-        "c5/fp64": [{"workgroups": 3072, "read_bytes": 2555100000, "write_bytes": 1218600000},
-                    {"workgroups": 2280, "read_bytes": 2554200000, "write_bytes": 1225700000}],
+    "2daf05dac7101246331d241dd6e1685cb2718dd6c21b7d2aa7f9b1f219baf924": {
+        "c5/fp64": [{"workgroups": 760, "read_bytes": 2589700000, "write_bytes": 1234500000},
+                    {"workgroups": 832, "read_bytes": 2565100000, "write_bytes": 1232300000},
+                    {"workgroups": 1104, "read_bytes": 2550600000, "write_bytes": 1229900000},
+                    {"workgroups": 1520, "read_bytes": 2546900000, "write_bytes": 1233500000},
+                    {"workgroups": 1624, "read_bytes": 2540400000, "write_bytes": 1231300000},
+                    {"workgroups": 2176, "read_bytes": 2589800000, "write_bytes": 1229100000},
+                    {"workgroups": 2280, "read_bytes": 2573800000, "write_bytes": 1227900000},
+                    {"workgroups": 3072, "read_bytes": 2570700000, "write_bytes": 1221800000},
+                    {"workgroups": 3248, "read_bytes": 2611800000, "write_bytes": 1219500000},
+                    {"workgroups": 4320, "read_bytes": 2709600000, "write_bytes": 1214500000},
+                    {"workgroups": 6488, "read_bytes": 2747500000, "write_bytes": 1205100000},
+                    {"workgroups": 8632, "read_bytes": 3023100000, "write_bytes": 1188500000},
+                    {"workgroups": 12944, "read_bytes": 3246800000, "write_bytes": 1187300000}],
+        "c5/fp32": [{"workgroups": 832, "read_bytes": 1262300000, "write_bytes": 623100000},
+                    {"workgroups": 1008, "read_bytes": 1288100000, "write_bytes": 626900000},
+                    {"workgroups": 1104, "read_bytes": 1278000000, "write_bytes": 622100000},
+                    {"workgroups": 1624, "read_bytes": 1245600000, "write_bytes": 616600000},
+                    {"workgroups": 2040, "read_bytes": 1268200000, "write_bytes": 616500000},
+                    {"workgroups": 2176, "read_bytes": 1271600000, "write_bytes": 615300000},
+                    {"workgroups": 3072, "read_bytes": 1262300000, "write_bytes": 607600000},
+                    {"workgroups": 3248, "read_bytes": 1281800000, "write_bytes": 606400000},
+                    {"workgroups": 4072, "read_bytes": 1314000000, "write_bytes": 605900000},
+                    {"workgroups": 4320, "read_bytes": 1323600000, "write_bytes": 600700000},
+                    {"workgroups": 6488, "read_bytes": 1342500000, "write_bytes": 590200000},
+                    {"workgroups": 8632, "read_bytes": 1442000000, "write_bytes": 585800000},
+                    {"workgroups": 12944, "read_bytes": 1495900000, "write_bytes": 580300000}],
     },
 }
 
@@ -127,9 +147,10 @@ def timed(torch, stream, fn):
 
 def run_grid(case, prec, steps, warmup, gauges=True, enclosed=False, bndout=1):
     """Whole-step throughput (gauges every 10 steps, maxwave every step, and
-    the enclosed-grid boundary series every `bndout` steps when `enclosed`),
-    with the step kernel's own launches timed by the library's event pairs
-    over the same timed steps."""
+    the enclosed-grid boundary series every `bndout` steps when `enclosed`);
+    then the same run again with the library's event pair around every
+    step-kernel launch (kernel_timing), which gives the kernel's own mean
+    launch duration over the timed steps."""
     import torch
     from paper_1410_0753_amd import clf
     esize = 4 if prec == clf.FP32 else 8
@@ -138,31 +159,41 @@ def run_grid(case, prec, steps, warmup, gauges=True, enclosed=False, bndout=1):
         kw = dict(bndout=bndout, max_enclosed=len(case.enclosed),
                   max_enclosed_points=sum(2 * (len(x) + len(y)) for x, y in case.enclosed),
                   series_capacity=(steps + warmup) // bndout + 8)
-    s = clf.Solver.from_case(case, precision=prec, gout=10, maxout=1, autotune=1,
-                             kernel_timing=1, gauge_capacity=(steps + warmup) // 10 + 8, **kw)
-    s.set_initial(case.eta0, case.u0, case.v0)
-    if gauges and case.gauges is not None:
-        s.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
-    if kw:
-        for ex, ey in case.enclosed:
-            s.add_enclosed_grid(ex, ey)
+
+    def solver(**extra):
+        s = clf.Solver.from_case(case, precision=prec, gout=10, maxout=1,
+                                 gauge_capacity=(steps + warmup) // 10 + 8, **kw, **extra)
+        s.set_initial(case.eta0, case.u0, case.v0)
+        if gauges and case.gauges is not None:
+            s.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
+        if kw:
+            for ex, ey in case.enclosed:
+                s.add_enclosed_grid(ex, ey)
+        s.step(warmup)
+        s.sync()
+        return s
+
+    s = solver(autotune=1)
     seg = int(s.query(clf.Q_SEGMENT))
-    s.step(warmup)
-    s.sync()
-    s.query(clf.Q_KERNEL_RESET)
+    blocks = int(s.query(clf.Q_BLOCKS))
     secs = timed(torch, s.stream, lambda: s.step(steps))
     s.sync()
+    e, _, _, w = s.state()
+    del s
+    # the kernel's launches alone, same launch shape
+    s = solver(segment=seg, kernel_timing=1)
+    s.query(clf.Q_KERNEL_RESET)
+    secs_timed = timed(torch, s.stream, lambda: s.step(steps))
     kernel_ms = s.query(clf.Q_KERNEL_MS)
     launches = int(s.query(clf.Q_KERNEL_LAUNCHES))
-    e, _, _, w = s.state()
+    del s
     log("%s %s: %.4f ms/step, kernel %.4f ms (%d launches), segment %d, max|eta| %.3f, wet %d" % (
         case.name, "fp32" if prec == clf.FP32 else "fp64", secs / steps * 1e3, kernel_ms,
         launches, seg, float(e.abs().max()), int(w.sum())))
     achieved = WORDS_PER_CELL_STEP * esize * case.cells / (kernel_ms * 1e-3)
-    blocks = int(s.query(clf.Q_BLOCKS))
-    del s
     return {"value": case.cells * steps / secs, "ms_per_step": secs / steps * 1e3,
             "segment": seg, "kernel_ms": kernel_ms, "kernel_launches": launches,
+            "ms_per_step_with_event_pairs": secs_timed / steps * 1e3,
             "achieved": achieved, "workgroups": blocks,
             "enclosed_grids": len(case.enclosed) if kw else 0}
 
