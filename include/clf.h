@@ -88,6 +88,11 @@ extern "C" {
 #define CLF_Q_KERNEL_MS 12
 #define CLF_Q_KERNEL_LAUNCHES 13
 #define CLF_Q_KERNEL_RESET 14
+/* 1 if the FP32 step kernel stages the rows of its march in LDS (FP32 grids
+ * whose fields exceed the 256 MiB last-level cache; the environment variable
+ * CLF_LDS_ROWS=0 or 1, read at init, forces it off or on).  The results are
+ * the same bits either way. */
+#define CLF_Q_LDS_ROWS 15
 
 typedef struct clf_ctx clf_ctx;
 
@@ -412,8 +417,8 @@ int clf_bands_read_maxwave(clf_bands* b, double* eta_max, double* speed_max);
 
 int clf_bands_sync(clf_bands* b);
 /* CLF_Q_MAX_CFL, CLF_Q_MIN_F, CLF_Q_SSL_PASSES of the whole grid; CLF_Q_STEP,
- * CLF_Q_TILES, CLF_Q_SEGMENT, CLF_Q_BLOCKS, CLF_Q_WIDE, CLF_Q_WORKSPACE of the
- * launch over all bands. */
+ * CLF_Q_TILES, CLF_Q_SEGMENT, CLF_Q_BLOCKS, CLF_Q_WIDE, CLF_Q_LDS_ROWS,
+ * CLF_Q_WORKSPACE of the launch over all bands. */
 int clf_bands_query(clf_bands* b, int what, double* value);
 const char* clf_bands_last_error(const clf_bands* b);
 int clf_bands_destroy(clf_bands* b);

@@ -26,7 +26,8 @@ WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
 FRICTION_EXPLICIT, FRICTION_SEMI_IMPLICIT = 0, 1
 OPEN_W, OPEN_E, OPEN_S, OPEN_N = 1, 2, 4, 8
 (Q_MAX_CFL, Q_SSL_PASSES, Q_STEP, Q_MIN_F, Q_WORKSPACE, Q_GAUGE_RECORDS, Q_TILES, Q_SEGMENT,
- Q_BLOCKS, Q_GRAPH_REPLAYS, Q_WIDE, Q_KERNEL_MS, Q_KERNEL_LAUNCHES, Q_KERNEL_RESET) = range(1, 15)
+ Q_BLOCKS, Q_GRAPH_REPLAYS, Q_WIDE, Q_KERNEL_MS, Q_KERNEL_LAUNCHES, Q_KERNEL_RESET,
+ Q_LDS_ROWS) = range(1, 16)
 
 # Every symbol include/clf.h declares.
 EXPORTS = ["clf_default_params", "clf_node_index", "clf_workspace_bytes", "clf_init", "clf_set_initial",

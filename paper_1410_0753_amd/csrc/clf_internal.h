@@ -38,6 +38,8 @@ enum : int {
   G_OPEN_S = 8192,
   G_OPEN_N = 16384,
   G_OPEN_ANY = G_OPEN_W | G_OPEN_E | G_OPEN_S | G_OPEN_N,
+  G_LDSROWS = 32768,   // FP32 2-D march: rows staged in LDS by direct global-to-LDS
+                       // loads (a launch mode; the results are the same bits)
 };
 
 // kernel orders

@@ -124,6 +124,76 @@ __device__ __forceinline__ bool wet_before_b(int f) {
 #ifndef CLF_PREFETCH32
 #define CLF_PREFETCH32 2
 #endif
+// Rows of the 2-D march are prefetched into registers P::kPrefetch rows
+// ahead of use, or (G_LDSROWS, FP32 variants for grids that stream from
+// HBM) staged in LDS through direct global-to-LDS loads kLdsAhead rows
+// ahead, with the maxwave of their output rows.  Staging gains where the
+// rows come from HBM; on a grid that the last-level cache holds, and in the
+// FP64 kernel, whose vector ALU is the busier unit, its extra instructions
+// cost more than it saves.
+constexpr int kLdsSlots = 4;               // LDS row slots per wavefront (a power of 2)
+constexpr int kLdsAhead = kLdsSlots - 1;   // rows in flight ahead of the one in use
+
+// Wait until at most N vector memory operations of this wavefront are
+// outstanding.  Vector memory operations complete in issue order, so this
+// waits for every operation issued before the last N.  The memory clobber
+// keeps the compiler from moving LDS reads above the wait.
+template <int N>
+__device__ __forceinline__ void wait_vmem() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// One direct global-to-LDS load of a dword per lane: lane l's dword lands at
+// lds + 4 l (bytes).
+__device__ __forceinline__ void dma_dword(const char* g, void* lds) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)g,
+                                   (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
+}
+
+// This lane's values of a row staged in LDS: four fields `stride` bytes apart
+// from byte address a, and the maxwave pair from am.  The reads are written
+// out here, with their wait in the same block, because the compiler would
+// otherwise wait for every direct-to-LDS load still in flight before any LDS
+// read; the order against those loads is kept by wait_vmem before this.
+template <class R>
+__device__ __forceinline__ void lds_row(unsigned a, unsigned am, R& h, R& d, R& u, R& v, R& e,
+                                        R& s2);
+template <>
+__device__ __forceinline__ void lds_row<double>(unsigned a, unsigned am, double& h, double& d,
+                                                double& u, double& v, double& e, double& s2) {
+  asm volatile(
+      "ds_read_b64 %0, %6\n\t"
+      "ds_read_b64 %1, %6 offset:512\n\t"
+      "ds_read_b64 %2, %6 offset:1024\n\t"
+      "ds_read_b64 %3, %6 offset:1536\n\t"
+      "ds_read_b64 %4, %7\n\t"
+      "ds_read_b64 %5, %7 offset:512\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(h), "=&v"(d), "=&v"(u), "=&v"(v), "=&v"(e), "=&v"(s2)
+      : "v"(a), "v"(am)
+      : "memory");
+}
+template <>
+__device__ __forceinline__ void lds_row<float>(unsigned a, unsigned am, float& h, float& d,
+                                               float& u, float& v, float& e, float& s2) {
+  asm volatile(
+      "ds_read_b32 %0, %6\n\t"
+      "ds_read_b32 %1, %6 offset:256\n\t"
+      "ds_read_b32 %2, %6 offset:512\n\t"
+      "ds_read_b32 %3, %6 offset:768\n\t"
+      "ds_read_b32 %4, %7\n\t"
+      "ds_read_b32 %5, %7 offset:256\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(h), "=&v"(d), "=&v"(u), "=&v"(v), "=&v"(e), "=&v"(s2)
+      : "v"(a), "v"(am)
+      : "memory");
+}
+
+template <class T>
+__device__ __forceinline__ unsigned lds_addr(T* p) {
+  return (unsigned)(uintptr_t)(__attribute__((address_space(3))) T*)p;
+}
 
 struct P64 {
   typedef double R;
@@ -469,7 +539,11 @@ struct P64 {
 //           + g (h_b - h_a) (w_a + w_b)/(c_a + c_b) ] / dx,   Q_M: minus sign,
 //   p' - p = -dt/2 (QL + QR) + lambda dt^2 (QR - QL)/(dx_l + dx_r),
 //   u' = u + (dp + dq)/2,  h' = h + d (8c + d)/16g with d = dp - dq,
-// which is zero to the bit for a lake at rest.
+// which is zero to the bit for a lake at rest.  Products that feed a sum
+// are fused (one rounding instead of two; the FP64 stages keep the written
+// order with separate roundings, which the oracle shares).  A fused
+// multiply-add of negated operands is the negated result, so mirror-image
+// nodes still get mirror-image bits.
 // ---------------------------------------------------------------------------
 struct P32 {
   typedef float R;
@@ -568,10 +642,8 @@ struct P32 {
     const float de = eb - ea;
     const float dh = (Db - Da) + de;
     const float lam2 = sw + sg * sc;
-    const float adv = 0.5f * lam2 * dw;
-    const float grav = kGf * de;
     const float cross = kGf * dh * (sw * __builtin_amdgcn_rcpf(sc));
-    return (adv + grav + sg * cross) * inv;
+    return __builtin_fmaf(0.5f * lam2, dw, __builtin_fmaf(kGf, de, sg * cross)) * inv;
   }
 
   static __device__ __forceinline__ float qt(float wa, float ta, float wb, float tb, float inv) {
@@ -581,7 +653,7 @@ struct P32 {
   static __device__ __forceinline__ float incr(const Par& p, float lam, float QL, float QR, float Qc,
                                                float iS) {
     const float first = (p.flags & G_SOLVER1) ? -(p.dt * Qc) : -(p.hdt * (QL + QR));
-    return first + ((lam * p.dt2) * (QR - QL)) * iS;
+    return __builtin_fmaf((lam * p.dt2) * (QR - QL), iS, first);
   }
 
   // the interface values of the three families (shared between the two
@@ -616,10 +688,8 @@ struct P32 {
     const float sw = wb + wa, dw = wb - wa, sc = cb + ca;
     const float dh = dD + de;
     const float lam2 = sw + sg * sc;
-    const float adv = 0.5f * lam2 * dw;
-    const float grav = kGf * de;
     const float cross = kGf * dh * (sw * __builtin_amdgcn_rcpf(sc));
-    return (adv + grav + sg * cross) * inv;
+    return __builtin_fmaf(0.5f * lam2, dw, __builtin_fmaf(kGf, de, sg * cross)) * inv;
   }
 
   static __device__ __forceinline__ C stage_cd_shared(const B& c, const Fx& FL, const Fx& FR,
@@ -678,23 +748,23 @@ struct P32 {
       dP = dP + s3;
       dM = dM - s3;
     }
-    float wv = Cw + 0.5f * (dP + dM);
+    float wv = __builtin_fmaf(0.5f, dP + dM, Cw);
     const float dd = dP - dM;
-    const float dh = (dd * (8.f * Cc + dd)) * p.inv16g;
-    const bool drained = 4.f * Cc + dd < 0.f;
+    const float dh = (dd * __builtin_fmaf(8.f, Cc, dd)) * p.inv16g;
+    const bool drained = __builtin_fmaf(4.f, Cc, dd) < 0.f;
     const float hv = drained ? 0.f : c.h + dh;
     const float ev = drained ? -CD : Ce + dh;
     if (p.flags & G_FRICTION) {
       // fr = dt g n^2 |U| h^(-4/3) through the hardware log2 / exp2.  The
       // -alpha dt term on p and q moves u by -alpha dt and leaves p - q
       // (hence h) unchanged, so it is applied to u directly.
-      const float sp = __builtin_amdgcn_sqrtf(Cw * Cw + Ct * Ct);
+      const float sp = __builtin_amdgcn_sqrtf(__builtin_fmaf(Cw, Cw, Ct * Ct));
       const float hm43 = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(c.h) * (-4.0f / 3.0f));
       const float fr = ((p.dt * p.gn2) * sp) * hm43;
       if (p.flags & G_FRIC_SEMI)
         wv = wv * __builtin_amdgcn_rcpf(1.f + fr);
       else
-        wv = wv - (fr < 1.f ? fr : 1.f) * Cw;
+        wv = __builtin_fmaf(-(fr < 1.f ? fr : 1.f), Cw, wv);
     }
     const bool wet = (c.f & F_WET) != 0;
     C o;
@@ -951,6 +1021,8 @@ constexpr int FL_ALL = G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N | G_WALLMODE | G_SO
 // grids whose field arrays exceed 4 GiB: the same three flag sets with
 // 64-bit addresses
 constexpr int FL_FAST_WIDE = FL_FAST | G_WIDE;
+constexpr int FL_FAST_LDS = FL_FAST | G_LDSROWS;
+constexpr int FL_FRIC_LDS = FL_FRIC | G_LDSROWS;
 constexpr int FL_FRIC_WIDE = FL_FRIC | G_WIDE;
 constexpr int FL_WIDE = FL_ALL | G_WIDE;
 
@@ -982,6 +1054,11 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
   // the wave index is uniform across the wavefront: say so, so that the
   // tile, the row counter and the row metrics live in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  // LDS ring of the 2-D march (G_LDSROWS): per wavefront and slot, a row
+  // of h, d, u, v and the maxwave pair of an output row
+  constexpr bool kLds = ORDER != ORD_X && (FL & G_LDSROWS) != 0;
+  __shared__ R lrow[kLds ? kLdsSlots : 1][WAVES_PER_BLOCK][4][WAVE];
+  __shared__ R lmw[kLds ? kLdsSlots : 1][WAVES_PER_BLOCK][2][WAVE];
   // grid-stride over the tile list: one tile per wavefront when the grid
   // covers the list, a persistent loop when it is launched smaller
   const int stride = gridDim.x * WAVES_PER_BLOCK;
@@ -1124,6 +1201,29 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
       // vertically adjacent segments read the rows around their common edge
       // at the same phase of their marches (both at the start or both at
       // the end), when one XCD's L2 can serve the second read.
+      // Rows staged in LDS: each lane loads dwords of the 64-column window
+      // (FP64: two loads of 64 dwords per field row, FP32: one), at byte
+      // offsets within the row that depend only on the column, so they are
+      // computed once per tile; the row itself enters through the scalar
+      // base address.
+      constexpr int kDw = sizeof(R) / 4;   // dwords per value
+      unsigned dma_off[kDw];
+#pragma unroll
+      for (int h = 0; h < kDw; ++h) {
+        const int d = h * WAVE + lane;     // dword of the window this lane loads
+        int col = tl.x0 - HALO + d / kDw;
+        col = col < 0 ? 0 : (col >= nx ? nx - 1 : col);
+        dma_off[h] = (unsigned)col * (unsigned)sizeof(R) + (unsigned)(d % kDw) * 4u;
+      }
+      auto dma_row = [&](const R* base, int r, R* lds) {
+        const int rc = r < 0 ? 0 : (r >= ny ? ny - 1 : r);
+        const char* g = (const char*)base + (size_t)rc * (size_t)nx * sizeof(R);
+#pragma unroll
+        for (int h = 0; h < kDw; ++h) dma_dword(g + dma_off[h], lds + h * (WAVE / kDw));
+      };
+      // vector memory operations one march row issues: the row's four fields,
+      // and the maxwave pair of an output row
+      constexpr int kVmRow = 4 * kDw, kVmMw = 2 * kDw;
       auto march = [&](auto dir) {
         constexpr int D = decltype(dir)::value;
         YPipe<P> yp;
@@ -1136,18 +1236,65 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
         // rows are loaded PF = P::kPrefetch march rows ahead of use (1 or 2:
         // the three slots hold the row in use and up to two in flight)
         constexpr int PF = P::kPrefetch;
-        load_row(r_first, pf[0]);
-        if (PF == 2) load_row(r_first + D, pf[1]);
-        load_mw(r_first - D * HALO, pm[0]);
-        // one march row in phase K: consume pf[K] (row r) and pm[K] (maxwave
-        // of the output row r - 3D); prefetch row r + PF D and the maxwave of
-        // the next output row
-        auto body = [&](auto phase, int r) {
+        // LDS ring: march row i sits in slot i % kLdsSlots, with the maxwave
+        // of its output row r - 3D; rows i + 1 .. i + kLdsAhead are in flight
+        auto issue_dir = [&](int i) {
+          const int r = r_first + D * i;
+          const int slot = i & (kLdsSlots - 1);
+          dma_row(cx.H, r, &lrow[slot][wave][0][0]);
+          dma_row(cx.D, r, &lrow[slot][wave][1][0]);
+          dma_row(cx.U, r, &lrow[slot][wave][2][0]);
+          dma_row(cx.V, r, &lrow[slot][wave][3][0]);
+          if (do_max) {
+            dma_row(cx.emax, r - D * HALO, &lmw[slot][wave][0][0]);
+            dma_row(cx.smax2, r - D * HALO, &lmw[slot][wave][1][0]);
+          }
+        };
+        if (kLds) {
+          // Every load issued before the march (the tile's column metrics)
+          // has landed, in a wait the compiler sees: the waits inside the
+          // march are its own, and without this one the compiler would wait
+          // for all loads in flight before the first use of those values
+          // in each row.  (simm16: vmcnt 0, expcnt and lgkmcnt not waited)
+          __builtin_amdgcn_s_waitcnt(0x0F70);
+#pragma unroll
+          for (int j = 0; j < kLdsAhead; ++j) issue_dir(j);
+        } else {
+          load_row(r_first, pf[0]);
+          if (PF == 2) load_row(r_first + D, pf[1]);
+          load_mw(r_first - D * HALO, pm[0]);
+        }
+        // one march row in phase K: consume row r and the maxwave of the
+        // output row r - 3D; prefetch the rows ahead
+        auto body = [&](auto phase, int r, int i) {
           constexpr int K = decltype(phase)::value;
-          A a = pf[K];
-          MW m = pm[K];
-          load_row(r + D * PF, pf[(K + PF) % 3]);
-          load_mw(r + D * (1 - HALO), pm[(K + 1) % 3]);
+          A a;
+          MW m;
+          if (kLds) {
+            // row i and its maxwave pair were issued kLdsAhead rows ago;
+            // the kLdsAhead - 1 rows issued since may still be in flight
+            if (do_max)
+              wait_vmem<(kLdsAhead - 1) * (kVmRow + kVmMw)>();
+            else
+              wait_vmem<(kLdsAhead - 1) * kVmRow>();
+            const int slot = i & (kLdsSlots - 1);
+            // x view: w = u, t = v
+            lds_row<R>(lds_addr(&lrow[slot][wave][0][lane]), lds_addr(&lmw[slot][wave][0][lane]),
+                       a.H, a.D, a.w, a.t, m.e, m.s2);
+            a.f = (col_in && r >= 0 && r < ny) ? F_EX : 0;
+            if (kRing) a.f |= ring_flag(cx.gflags, xc, r, nx, ny);
+            if (kOpen) a.f |= open_flag(cx.gflags, xc, r, nx, ny);
+            if (!do_max) {
+              m.e = 0;
+              m.s2 = 0;
+            }
+            issue_dir(i + kLdsAhead);
+          } else {
+            a = pf[K];
+            m = pm[K];
+            load_row(r + D * PF, pf[(K + PF) % 3]);
+            load_mw(r + D * (1 - HALO), pm[(K + 1) % 3]);
+          }
           const int ro = r - D * HALO;
           const bool writes = D > 0 ? ro >= tl.y0 : ro <= ylast;
           if (ORDER == ORD_YX) {
@@ -1190,12 +1337,15 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
         // one rotation (no register copies); the last 0-2 rows after it
         int i = 0;
         for (; i + 3 <= npush; i += 3) {
-          body(std::integral_constant<int, 0>(), r_first + D * i);
-          body(std::integral_constant<int, 1>(), r_first + D * (i + 1));
-          body(std::integral_constant<int, 2>(), r_first + D * (i + 2));
+          body(std::integral_constant<int, 0>(), r_first + D * i, i);
+          body(std::integral_constant<int, 1>(), r_first + D * (i + 1), i + 1);
+          body(std::integral_constant<int, 2>(), r_first + D * (i + 2), i + 2);
         }
-        if (i < npush) body(std::integral_constant<int, 0>(), r_first + D * i);
-        if (i + 1 < npush) body(std::integral_constant<int, 1>(), r_first + D * (i + 1));
+        if (i < npush) body(std::integral_constant<int, 0>(), r_first + D * i, i);
+        if (i + 1 < npush) body(std::integral_constant<int, 1>(), r_first + D * (i + 1), i + 1);
+        // the rows issued beyond the march must land before the LDS ring is
+        // reused (next tile) or released (end of the wavefront)
+        if (kLds) wait_vmem<0>();
       };
       if (rev)
         march(std::integral_constant<int, -1>());
@@ -1500,7 +1650,7 @@ hipError_t launch_step(int fp32, int order, int gflags, const GridDesc* grids, c
                        int ntiles, StepState* st, int parity, int do_max, int nblocks,
                        hipStream_t s, int rec_slot) {
   dim3 grid(nblocks), block(WAVE * WAVES_PER_BLOCK);
-  const int base = gflags & ~G_WIDE;
+  const int base = gflags & ~(G_WIDE | G_LDSROWS);
   const bool fast = (base & ~FL_FAST) == 0;
   const bool fric = (base & ~FL_FRIC) == 0;
   const bool fric_semi = (base & ~FL_FRIC_SEMI) == 0;
@@ -1529,7 +1679,14 @@ hipError_t launch_step(int fp32, int order, int gflags, const GridDesc* grids, c
                                    do_max, rec_slot);
     }
   } else if (fp32) {
-    if (fast)
+    const bool lds = (gflags & G_LDSROWS) != 0;
+    if (fast && lds)
+      launch_order<P32, FL_FAST_LDS>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                     do_max, rec_slot);
+    else if (fric && lds)
+      launch_order<P32, FL_FRIC_LDS>(order, grid, block, s, grids, tiles, ntiles, st, parity,
+                                     do_max, rec_slot);
+    else if (fast)
       launch_order<P32, FL_FAST>(order, grid, block, s, grids, tiles, ntiles, st, parity,
                                  do_max, rec_slot);
     else if (fric)
@@ -1591,7 +1748,7 @@ static hipError_t occupancy_of(int order, int* n) {
 
 hipError_t step_blocks_per_cu(int fp32, int order, int gflags, int* n) {
   *n = 0;
-  const int base = gflags & ~G_WIDE;
+  const int base = gflags & ~(G_WIDE | G_LDSROWS);
   const bool fast = (base & ~FL_FAST) == 0;
   const bool fric = (base & ~FL_FRIC) == 0;
   const bool fric_semi = (base & ~FL_FRIC_SEMI) == 0;
@@ -1606,6 +1763,8 @@ hipError_t step_blocks_per_cu(int fp32, int order, int gflags, int* n) {
                 : (fric ? occupancy_of<P64, FL_FRIC_WIDE>(order, n)
                         : occupancy_of<P64, FL_WIDE>(order, n));
   }
+  if (fp32 && (gflags & G_LDSROWS) && (fast || fric))
+    return fast ? occupancy_of<P32, FL_FAST_LDS>(order, n) : occupancy_of<P32, FL_FRIC_LDS>(order, n);
   if (fp32)
     return fast ? occupancy_of<P32, FL_FAST>(order, n)
                 : fric      ? occupancy_of<P32, FL_FRIC>(order, n)

@@ -623,6 +623,18 @@ static bool wide_offsets(int nx, int ny, int fp32) {
   return e && e[0] == '1';
 }
 
+// FP32 grids whose fields stream from HBM each step (more than the 256 MiB
+// last-level cache holds: h, u, v twice, depth and the maxwave pair) stage
+// the rows of the march in LDS; the results are the same bits either way.
+// The environment variable CLF_LDS_ROWS, read at init, forces it on (1) or
+// off (0) for any FP32 grid, so that both can be checked on small ones.
+static bool lds_rows(int nx, int ny, int fp32) {
+  if (!fp32) return false;
+  const char* e = std::getenv("CLF_LDS_ROWS");
+  if (e && (e[0] == '0' || e[0] == '1')) return e[0] == '1';
+  return (long long)nx * ny * 9 * 4 > (256LL << 20);
+}
+
 static int validate(const clf_grid* g, const clf_params* p, clf_ctx* c);
 
 }  // extern "C"
@@ -662,6 +674,7 @@ int grid_flags(const clf_grid& g, const clf_params& p) {
   if (p.open_sides & 4) flags |= G_OPEN_S;
   if (p.open_sides & 8) flags |= G_OPEN_N;
   if (wide_offsets(g.nx, g.ny, fp32)) flags |= G_WIDE;
+  else if (lds_rows(g.nx, g.ny, fp32)) flags |= G_LDSROWS;
   if (!fp32 && p.h_min < 1e-200) flags |= G_TINYH;
   return flags;
 }
@@ -1412,6 +1425,7 @@ int clf_query(clf_ctx* c, int what, double* value) {
     case CLF_Q_BLOCKS: *value = eff_blocks(c->nblocks, c->p.persistent_blocks); break;
     case CLF_Q_GRAPH_REPLAYS: *value = (double)c->graph_replays; break;
     case CLF_Q_WIDE: *value = (c->gd.flags & G_WIDE) ? 1.0 : 0.0; break;
+    case CLF_Q_LDS_ROWS: *value = (c->gd.flags & G_LDSROWS) ? 1.0 : 0.0; break;
     case CLF_Q_KERNEL_MS:
     case CLF_Q_KERNEL_LAUNCHES:
     case CLF_Q_KERNEL_RESET: {
@@ -1987,6 +2001,7 @@ int clf_ensemble_query(clf_ens* e, int what, double* value) {
     case CLF_Q_BLOCKS: *value = eff_blocks(e->nblocks, e->p.persistent_blocks); break;
     case CLF_Q_GRAPH_REPLAYS: *value = (double)e->graph_replays; break;
     case CLF_Q_WIDE: *value = (e->gflags & G_WIDE) ? 1.0 : 0.0; break;
+    case CLF_Q_LDS_ROWS: *value = (e->gflags & G_LDSROWS) ? 1.0 : 0.0; break;
     case CLF_Q_WORKSPACE: {
       double tot = 0;
       for (auto* c : e->m) tot += (double)c->L.total;
