@@ -3,7 +3,7 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W]
                     [--workload c5|c2|c1|ensemble|adjoint|c5search]
                     [--precision fp64|fp32] [--no-cpu] [--no-extras] [--profile]
-                    [--calibrate-copy]
+                    [--segment N] [--calibrate-copy]
 
 Headline (default): the 8000 x 6000 spherical grid at 0.5 arc-minute (seeded
 synthetic coast, shelf, slope, plane beaches at 1:50 and islands; 3 m dipole
@@ -66,33 +66,33 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1410_0753_amd", "csrc", "clf_kernels.hip"
 # shape; an entry applies only to a launch of the same workgroup count
 # (segment length), which the autotuner may choose differently run to run.
 TRAFFIC = {
-    "2daf05dac7101246331d241dd6e1685cb2718dd6c21b7d2aa7f9b1f219baf924": {
-        "c5/fp64": [{"workgroups": 760, "read_bytes": 2589700000, "write_bytes": 1234500000},
-                    {"workgroups": 832, "read_bytes": 2565100000, "write_bytes": 1232300000},
-                    {"workgroups": 1104, "read_bytes": 2550600000, "write_bytes": 1229900000},
-                    {"workgroups": 1520, "read_bytes": 2546900000, "write_bytes": 1233500000},
-                    {"workgroups": 1624, "read_bytes": 2540400000, "write_bytes": 1231300000},
-                    {"workgroups": 2176, "read_bytes": 2589800000, "write_bytes": 1229100000},
-                    {"workgroups": 2280, "read_bytes": 2573800000, "write_bytes": 1227900000},
-                    {"workgroups": 3072, "read_bytes": 2570700000, "write_bytes": 1221800000},
-                    {"workgroups": 3248, "read_bytes": 2611800000, "write_bytes": 1219500000},
-                    {"workgroups": 4320, "read_bytes": 2709600000, "write_bytes": 1214500000},
-                    {"workgroups": 6488, "read_bytes": 2747500000, "write_bytes": 1205100000},
-                    {"workgroups": 8632, "read_bytes": 3023100000, "write_bytes": 1188500000},
-                    {"workgroups": 12944, "read_bytes": 3246800000, "write_bytes": 1187300000}],
-        "c5/fp32": [{"workgroups": 832, "read_bytes": 1262300000, "write_bytes": 623100000},
-                    {"workgroups": 1008, "read_bytes": 1288100000, "write_bytes": 626900000},
-                    {"workgroups": 1104, "read_bytes": 1278000000, "write_bytes": 622100000},
-                    {"workgroups": 1624, "read_bytes": 1245600000, "write_bytes": 616600000},
-                    {"workgroups": 2040, "read_bytes": 1268200000, "write_bytes": 616500000},
-                    {"workgroups": 2176, "read_bytes": 1271600000, "write_bytes": 615300000},
-                    {"workgroups": 3072, "read_bytes": 1262300000, "write_bytes": 607600000},
-                    {"workgroups": 3248, "read_bytes": 1281800000, "write_bytes": 606400000},
-                    {"workgroups": 4072, "read_bytes": 1314000000, "write_bytes": 605900000},
-                    {"workgroups": 4320, "read_bytes": 1323600000, "write_bytes": 600700000},
-                    {"workgroups": 6488, "read_bytes": 1342500000, "write_bytes": 590200000},
-                    {"workgroups": 8632, "read_bytes": 1442000000, "write_bytes": 585800000},
-                    {"workgroups": 12944, "read_bytes": 1495900000, "write_bytes": 580300000}],
+    "7861ec5e782c374fb3327720290bd26bcf5c8e473d704610f5febc24014c678e": {
+        "c5/fp64": [{"workgroups": 760, "read_bytes": 2583400000, "write_bytes": 1234200000},
+                    {"workgroups": 832, "read_bytes": 2561900000, "write_bytes": 1232000000},
+                    {"workgroups": 1104, "read_bytes": 2546100000, "write_bytes": 1229700000},
+                    {"workgroups": 1520, "read_bytes": 2546400000, "write_bytes": 1233100000},
+                    {"workgroups": 1624, "read_bytes": 2542600000, "write_bytes": 1230900000},
+                    {"workgroups": 2176, "read_bytes": 2589900000, "write_bytes": 1228900000},
+                    {"workgroups": 2280, "read_bytes": 2573000000, "write_bytes": 1227400000},
+                    {"workgroups": 3072, "read_bytes": 2570900000, "write_bytes": 1221300000},
+                    {"workgroups": 3248, "read_bytes": 2611500000, "write_bytes": 1218900000},
+                    {"workgroups": 4320, "read_bytes": 2709000000, "write_bytes": 1218600000},
+                    {"workgroups": 6488, "read_bytes": 2746900000, "write_bytes": 1197800000},
+                    {"workgroups": 8632, "read_bytes": 3025400000, "write_bytes": 1187900000},
+                    {"workgroups": 12944, "read_bytes": 3254200000, "write_bytes": 1187200000}],
+        "c5/fp32": [{"workgroups": 832, "read_bytes": 1204100000, "write_bytes": 587300000},
+                    {"workgroups": 1008, "read_bytes": 1306700000, "write_bytes": 622000000},
+                    {"workgroups": 1104, "read_bytes": 1287100000, "write_bytes": 615100000},
+                    {"workgroups": 1624, "read_bytes": 1285800000, "write_bytes": 612800000},
+                    {"workgroups": 2040, "read_bytes": 1303300000, "write_bytes": 615800000},
+                    {"workgroups": 2176, "read_bytes": 1302500000, "write_bytes": 615400000},
+                    {"workgroups": 3072, "read_bytes": 1318500000, "write_bytes": 605800000},
+                    {"workgroups": 3248, "read_bytes": 1319400000, "write_bytes": 603100000},
+                    {"workgroups": 4072, "read_bytes": 1346300000, "write_bytes": 593000000},
+                    {"workgroups": 4320, "read_bytes": 1357000000, "write_bytes": 595600000},
+                    {"workgroups": 6488, "read_bytes": 1431400000, "write_bytes": 580600000},
+                    {"workgroups": 8632, "read_bytes": 1492200000, "write_bytes": 578600000},
+                    {"workgroups": 12944, "read_bytes": 1587600000, "write_bytes": 577600000}],
     },
 }
 
@@ -145,12 +145,13 @@ def timed(torch, stream, fn):
     return e0.elapsed_time(e1) / 1e3
 
 
-def run_grid(case, prec, steps, warmup, gauges=True, enclosed=False, bndout=1):
+def run_grid(case, prec, steps, warmup, gauges=True, enclosed=False, bndout=1, segment=None):
     """Whole-step throughput (gauges every 10 steps, maxwave every step, and
     the enclosed-grid boundary series every `bndout` steps when `enclosed`);
     then the same run again with the library's event pair around every
     step-kernel launch (kernel_timing), which gives the kernel's own mean
-    launch duration over the timed steps."""
+    launch duration over the timed steps.  The segment length is autotuned
+    unless `segment` fixes it."""
     import torch
     from paper_1410_0753_amd import clf
     esize = 4 if prec == clf.FP32 else 8
@@ -173,7 +174,7 @@ def run_grid(case, prec, steps, warmup, gauges=True, enclosed=False, bndout=1):
         s.sync()
         return s
 
-    s = solver(autotune=1)
+    s = solver(autotune=1) if segment is None else solver(segment=segment)
     seg = int(s.query(clf.Q_SEGMENT))
     blocks = int(s.query(clf.Q_BLOCKS))
     secs = timed(torch, s.stream, lambda: s.step(steps))
@@ -466,6 +467,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="run for profilers: at most 200 timed steps, no CPU leg, no extras")
+    ap.add_argument("--segment", type=int, default=None,
+                    help="fix the segment length (rows per tile) instead of autotuning it, "
+                         "so that profiler passes run one launch shape")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run the streaming probes once on 256 MiB (counter calibration)")
     args = ap.parse_args()
@@ -517,7 +521,7 @@ def main():
     enclosed = args.workload == "c5"
     log("generating workload", args.workload)
     case = make_case(args.workload)
-    head = run_grid(case, prec, args.steps, args.warmup, enclosed=enclosed)
+    head = run_grid(case, prec, args.steps, args.warmup, enclosed=enclosed, segment=args.segment)
     probes = None if args.profile else probe_rates()
     traffic = None
     tr = traffic_entry(kernel_sha(), "%s/%s" % (args.workload, args.precision),
