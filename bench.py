@@ -387,7 +387,9 @@ def run_adjoint(steps=3000, cpu_fd=False):
         e[k] = h
         fd[k] = (loss(c0 + e) - loss(c0 - e)) / (2 * h)
     t_fd = time.perf_counter() - t0
-    rel = float(np.max(np.abs(g - fd)) / np.max(np.abs(fd)))
+    # a run too short for the waves to reach the gauges has a zero gradient
+    fdmax = float(np.max(np.abs(fd)))
+    rel = float(np.max(np.abs(g - fd)) / fdmax) if fdmax > 0 else None
     extra = {}
     if cpu_fd:
         # the same finite-difference gradient on the host oracle, estimated
