@@ -1271,12 +1271,26 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
           A a;
           MW m;
           if (kLds) {
-            // row i and its maxwave pair were issued kLdsAhead rows ago;
-            // the kLdsAhead - 1 rows issued since may still be in flight
-            if (do_max)
-              wait_vmem<(kLdsAhead - 1) * (kVmRow + kVmMw)>();
-            else
-              wait_vmem<(kLdsAhead - 1) * kVmRow>();
+            // Row i and its maxwave pair were issued kLdsAhead rows ago; the
+            // kLdsAhead - 1 rows issued since may still be in flight. From
+            // step 2 HALO + kLdsAhead on, each of the kLdsAhead steps since
+            // that issue has also stored its output row (h, u, v: one store
+            // each, issued after the step's loads), so those stores may be
+            // in flight as well. (The conditional maxwave and gauge stores
+            // only add to the operations issued after row i.)
+            constexpr int kRowOps = kVmRow + kVmMw, kRowOps0 = kVmRow;
+            constexpr int kStores = kLdsAhead * 3;
+            if (i >= 2 * HALO + kLdsAhead) {
+              if (do_max)
+                wait_vmem<(kLdsAhead - 1) * kRowOps + kStores>();
+              else
+                wait_vmem<(kLdsAhead - 1) * kRowOps0 + kStores>();
+            } else {
+              if (do_max)
+                wait_vmem<(kLdsAhead - 1) * kRowOps>();
+              else
+                wait_vmem<(kLdsAhead - 1) * kRowOps0>();
+            }
             const int slot = i & (kLdsSlots - 1);
             // x view: w = u, t = v
             lds_row<R>(lds_addr(&lrow[slot][wave][0][lane]), lds_addr(&lmw[slot][wave][0][lane]),
