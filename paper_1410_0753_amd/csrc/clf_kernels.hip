@@ -144,6 +144,16 @@ __device__ __forceinline__ void wait_vmem() {
   asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
+// A wavefront-uniform pointer passed through readfirstlane: the compiler can
+// then not fold per-lane terms into it, and forms it with scalar
+// instructions.
+__device__ __forceinline__ const char* uniform_ptr(const char* p) {
+  const unsigned long long a = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+  return (const char*)(((unsigned long long)hi << 32) | lo);
+}
+
 // One direct global-to-LDS load of a dword per lane: lane l's dword lands at
 // lds + 4 l (bytes).
 __device__ __forceinline__ void dma_dword(const char* g, void* lds) {
@@ -1057,7 +1067,12 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
   // LDS ring of the 2-D march (G_LDSROWS): per wavefront and slot, a row
   // of h, d, u, v and the maxwave pair of an output row
   constexpr bool kLds = ORDER != ORD_X && (FL & G_LDSROWS) != 0;
-  __shared__ R lrow[kLds ? kLdsSlots : 1][WAVES_PER_BLOCK][4][WAVE];
+  // In FP32 the row slots are padded (7 field rows for 4): 36 KB per
+  // workgroup hold residency at 4 workgroups, 16 waves, per CU. Without the
+  // padding the kernel fits 5 (96 VGPRs), and the 8000x6000 step was 2%
+  // slower at every segment length (more row streams in flight at once).
+  constexpr int kLdsFieldRows = kLds && std::is_same<P, P32>::value ? 7 : 4;
+  __shared__ R lrow[kLds ? kLdsSlots : 1][WAVES_PER_BLOCK][kLdsFieldRows][WAVE];
   __shared__ R lmw[kLds ? kLdsSlots : 1][WAVES_PER_BLOCK][2][WAVE];
   // grid-stride over the tile list: one tile per wavefront when the grid
   // covers the list, a persistent loop when it is launched smaller
@@ -1217,7 +1232,13 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
       }
       auto dma_row = [&](const R* base, int r, R* lds) {
         const int rc = r < 0 ? 0 : (r >= ny ? ny - 1 : r);
-        const char* g = (const char*)base + (size_t)rc * (size_t)nx * sizeof(R);
+        // The row's address, formed by scalar instructions (its byte offset
+        // is below 4 GiB: the staged form is not used with 64-bit
+        // addresses); otherwise the compiler folds the row offset into a
+        // per-lane 64-bit multiply-add for every load, and keeps a 64-bit
+        // base-plus-lane-offset pair per load alive across the march.
+        const unsigned rowoff = (unsigned)rc * (unsigned)nx * (unsigned)sizeof(R);
+        const char* g = uniform_ptr((const char*)base + rowoff);
 #pragma unroll
         for (int h = 0; h < kDw; ++h) dma_dword(g + dma_off[h], lds + h * (WAVE / kDw));
       };
