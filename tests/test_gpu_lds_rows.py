@@ -114,3 +114,68 @@ def test_lds_rows_by_footprint(clf):
         e = s.state()[0].cpu().numpy()
         assert np.array_equal(e, np.zeros_like(e))   # a lake at rest stays at rest
         del s
+
+
+class _Env:
+    def __init__(self, value):
+        self.value = value
+
+    def __enter__(self):
+        self.old = os.environ.get("CLF_LDS_ROWS")
+        os.environ["CLF_LDS_ROWS"] = self.value
+
+    def __exit__(self, *a):
+        if self.old is None:
+            del os.environ["CLF_LDS_ROWS"]
+        else:
+            os.environ["CLF_LDS_ROWS"] = self.old
+
+
+def test_lds_rows_in_ensembles_and_bands(clf):
+    # members of uneven size (strips not a multiple of four, ragged last
+    # segments) in one launch, and y-bands with their halo exchange
+    cases = [synth.random_small(40 + k, 70 + 23 * k, 45 + 11 * k, land=True) for k in range(3)]
+    out = {}
+    for mode in ("1", "0"):
+        with _Env(mode):
+            ens = clf.Ensemble(cases, precision=clf.FP32, graph_steps=0)
+            assert ens.query(clf.Q_LDS_ROWS) == int(mode)
+            for i, c in enumerate(cases):
+                ens.set_initial(i, 3.0 * c.eta0, c.u0, c.v0)
+            ens.step(13)
+            st = [[t.cpu().numpy() for t in ens.state(i)] for i in range(len(cases))]
+            bands = clf.Bands.from_case(cases[2], 3, precision=clf.FP32)
+            assert bands.query(clf.Q_LDS_ROWS) == int(mode)
+            bands.set_initial(3.0 * cases[2].eta0, cases[2].u0, cases[2].v0)
+            bands.step(13)
+            out[mode] = (st, _fields(bands))
+            del ens, bands
+    for i in range(len(cases)):
+        for a, b in zip(out["1"][0][i], out["0"][0][i]):
+            assert np.array_equal(a, b), "ensemble member %d" % i
+    for a, b in zip(out["1"][1], out["0"][1]):
+        assert np.array_equal(a, b), "bands"
+
+
+def test_lds_rows_in_the_static_entry_point(clf):
+    import torch
+    case = synth.random_small(44, 97, 52, land=True, coord=synth.SPHERICAL)
+    ctx = clf.Solver.from_case(case, precision=clf.FP32)
+    ctx.set_initial(3.0 * case.eta0, case.u0, case.v0)
+    e, u, v, w = (t.cpu().numpy() for t in ctx.state())
+    d = ctx.depth().cpu().numpy()
+    eta = np.where(w.astype(bool), e, -d)
+    res = {}
+    for mode in ("1", "0"):
+        D, H, U, V = (torch.tensor(a.astype(np.float32), device="cuda") for a in (d, eta, u, v))
+        b = [torch.empty_like(H) for _ in range(3)]
+        em, sm = torch.zeros_like(H), torch.zeros_like(H)
+        with _Env(mode):
+            which, bad = clf.step_static(case.x, case.y, case.coord, D, (H, U, V), tuple(b), 9,
+                                         case.dt, eta_max=em, speed2_max=sm,
+                                         precision=clf.FP32, h_min=case.h_min)
+        assert not bad
+        fin = (H, U, V) if which == 0 else tuple(b)
+        res[mode] = [t.cpu().numpy() for t in fin] + [em.cpu().numpy(), sm.cpu().numpy()]
+    for a, b in zip(res["1"], res["0"]):
+        assert np.array_equal(a, b)
