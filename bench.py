@@ -476,8 +476,8 @@ def main():
                     help="also run the streaming probes once on 256 MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: every GPU box here has one, and the library's "
-              "y-band decomposition (clf_bands) runs its bands on one device; use --gpus 1",
+        print("bench.py measures one GPU only: the library runs on one device (its y-band "
+              "decomposition, clf_bands, runs all bands on that device); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     if args.profile:
