@@ -478,15 +478,18 @@ struct P64 {
       Mn = Mn - s3;
     }
     // Manning friction: fr = dt g n^2 |U| / h^(4/3) with h^(-1/3) from a
-    // single-precision seed (hardware log2 / exp2) and two Newton steps
-    // r <- r (4 - h r^3) / 3: no libm cbrt and no division; agrees with the
-    // direct form to rounding
+    // single-precision seed (hardware log2 / exp2) and one Newton step
+    // r <- r (4 - h r^3) / 3 (relative error about 1e-13), and |U| from the
+    // square root without argument rescaling (speeds below 1e-115 m/s count
+    // as 0): no libm cbrt and no division. The friction term agrees with the
+    // direct form to about 1e-13 of itself; the rest of the update is the
+    // oracle's operation order.
     double fr = 0.0;
     if (p.flags & G_FRICTION) {
-      double sp = sqrt(Cw * Cw + Ct * Ct);
+      const double s2 = Cw * Cw + Ct * Ct;
+      const double sp = s2 < 0x1p-767 ? 0.0 : sqrt_large(s2);
       const double h = c.H;
       double r = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)h) * (-1.0f / 3.0f));
-      r = r * ((4.0 - h * ((r * r) * r)) * (1.0 / 3.0));
       r = r * ((4.0 - h * ((r * r) * r)) * (1.0 / 3.0));
       const double r2 = r * r;
       fr = ((p.dt * p.gn2) * sp) * (r2 * r2);
