@@ -1055,14 +1055,16 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
   typedef typename P::A A;
   typedef typename P::C C;
   // Each interface is evaluated once and handed to the node on its other
-  // side, except in the y pipeline of the FP64 friction variants and of the
-  // general variants (both forms give the same bits). In the first, the
-  // carried interface values would raise register use past the three
-  // resident waves per SIMD. In the second, solver1 takes the per-node form
-  // at run time, and with both forms in one kernel the FP32 pipeline
-  // windows were left in scratch memory (four times slower).
-  constexpr bool kShY = !(std::is_same<P, P64>::value && (FL & G_FRICTION) != 0) &&
-                        (FL & G_SOLVER1) == 0;
+  // side, except in the y pipeline of the FP64 variants with the
+  // semi-implicit friction option and of the general variants (both forms
+  // give the same bits). In the first, the carried interface values would
+  // raise register use past the three resident waves per SIMD (the explicit
+  // friction variant fits: 163 VGPRs). In the second, solver1 takes the
+  // per-node form at run time, and with both forms in one kernel the FP32
+  // pipeline windows were left in scratch memory (four times slower).
+  constexpr bool kShY =
+      !(std::is_same<P, P64>::value && (FL & G_FRICTION) != 0 && (FL & G_FRIC_SEMI) != 0) &&
+      (FL & G_SOLVER1) == 0;
   const int lane = threadIdx.x & (WAVE - 1);
   // the wave index is uniform across the wavefront: say so, so that the
   // tile, the row counter and the row metrics live in scalar registers
