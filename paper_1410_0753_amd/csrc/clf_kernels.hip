@@ -224,15 +224,17 @@ struct P64 {
     int flags;
   };
 
+  // (a) marks the wet nodes. A node in the grid at or below the threshold is
+  // dry; its values are not emptied here, because nothing that reaches a
+  // result reads them: its neighbours take its mirror ghost in (c)+(d), (b)
+  // reads wet neighbours and the dry node's own depth only, (b) overwrites
+  // a flooded node, and (d) replaces its own update by the dry state. (The
+  // oracle empties it, as step (a) is written; the results are the same
+  // bits.)
   static __device__ __forceinline__ void stage_a(A& a, const Par& p) {
-    // branch-free: a node in the grid at or below the threshold is emptied
     const bool ex = (a.f & F_EX) != 0;
     const bool wet = a.H > p.hmin;
-    const bool dry = ex && !wet;
     a.f |= (ex && wet) ? F_WET : 0;
-    a.H = dry ? 0.0 : a.H;
-    a.w = dry ? 0.0 : a.w;
-    a.t = dry ? 0.0 : a.t;
   }
 
   static __device__ __forceinline__ B stage_b(const A& l, const A& c, const A& r, const Par& p) {
@@ -573,14 +575,11 @@ struct P32 {
     int flags;
   };
 
+  // (a): as in the FP64 stages, dry nodes are only marked
   static __device__ __forceinline__ void stage_a(A& a, const Par& p) {
     const bool ex = (a.f & F_EX) != 0;
     const bool wet = a.D + a.H > p.hmin;
-    const bool dry = ex && !wet;
     a.f |= (ex && wet) ? F_WET : 0;
-    a.H = dry ? -a.D : a.H;
-    a.w = dry ? 0.f : a.w;
-    a.t = dry ? 0.f : a.t;
   }
 
   static __device__ __forceinline__ B stage_b(const A& l, const A& c, const A& r, const Par& p) {
