@@ -662,10 +662,12 @@ struct P32 {
     return (0.5f * (wb + wa) * (tb - ta)) * inv;
   }
 
+  // dt2iS = dt^2 / (Delta_l + Delta_r), formed once per node for the three
+  // families
   static __device__ __forceinline__ float incr(const Par& p, float lam, float QL, float QR, float Qc,
-                                               float iS) {
+                                               float dt2iS) {
     const float first = (p.flags & G_SOLVER1) ? -(p.dt * Qc) : -(p.hdt * (QL + QR));
-    return __builtin_fmaf((lam * p.dt2) * (QR - QL), iS, first);
+    return __builtin_fmaf(lam * (QR - QL), dt2iS, first);
   }
 
   // the interface values of the three families (shared between the two
@@ -752,9 +754,10 @@ struct P32 {
                                              float QMc, float QTc, float iS, float tanR,
                                              const Par& p) {
     const float Cw = c.w, Ct = c.t, CD = c.D, Cc = c.c, Ce = c.H;
-    float dP = incr(p, Cw + Cc, QPL, QPR, QPc, iS);
-    float dM = incr(p, Cw - Cc, QML, QMR, QMc, iS);
-    const float dT = incr(p, Cw, QTL, QTR, QTc, iS);
+    const float dt2iS = p.dt2 * iS;
+    float dP = incr(p, Cw + Cc, QPL, QPR, QPc, dt2iS);
+    float dM = incr(p, Cw - Cc, QML, QMR, QMc, dt2iS);
+    const float dT = incr(p, Cw, QTL, QTR, QTc, dt2iS);
     if (tanR != 0.f) {
       const float s3 = ((p.dt * Cc) * Cw) * tanR;
       dP = dP + s3;
