@@ -767,8 +767,6 @@ struct P32 {
     const float dd = dP - dM;
     const float dh = (dd * __builtin_fmaf(8.f, Cc, dd)) * p.inv16g;
     const bool drained = __builtin_fmaf(4.f, Cc, dd) < 0.f;
-    const float hv = drained ? 0.f : c.h + dh;
-    const float ev = drained ? -CD : Ce + dh;
     if (p.flags & G_FRICTION) {
       // fr = dt g n^2 |U| h^(-4/3) through the hardware log2 / exp2.  The
       // -alpha dt term on p and q moves u by -alpha dt and leaves p - q
@@ -782,11 +780,14 @@ struct P32 {
         wv = __builtin_fmaf(-(fr < 1.f ? fr : 1.f), Cw, wv);
     }
     const bool wet = (c.f & F_WET) != 0;
+    // a drained or dry node holds no water (one select per field: the two
+    // conditions are combined as lane masks)
+    const bool holds = wet && !drained;
     C o;
-    o.H = wet ? ev : -CD;
+    o.H = holds ? Ce + dh : -CD;
     o.w = wet ? wv : 0.f;
     o.t = wet ? Ct + dT : 0.f;
-    o.h = wet ? hv : 0.f;
+    o.h = holds ? c.h + dh : 0.f;
     if ((p.flags & (G_FIX_W | G_FIX_E | G_FIX_S | G_FIX_N)) && (c.f & F_FIX)) {
       o.H = c.H; o.w = c.w; o.t = c.t; o.h = c.h;
     }
