@@ -66,33 +66,33 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1410_0753_amd", "csrc", "clf_kernels.hip"
 # shape; an entry applies only to a launch of the same workgroup count
 # (segment length), which the autotuner may choose differently run to run.
 TRAFFIC = {
-    "42c65d8e2ae0ec0c55da08d0619616198daf001ebb309b784a0d3606c2bf0ab3": {
-        "c5/fp64": [{"workgroups": 760, "read_bytes": 2585500000, "write_bytes": 1234600000},
-                    {"workgroups": 832, "read_bytes": 2558600000, "write_bytes": 1232100000},
-                    {"workgroups": 1104, "read_bytes": 2547400000, "write_bytes": 1230100000},
-                    {"workgroups": 1520, "read_bytes": 2545800000, "write_bytes": 1233600000},
-                    {"workgroups": 1624, "read_bytes": 2540200000, "write_bytes": 1231100000},
-                    {"workgroups": 2176, "read_bytes": 2589300000, "write_bytes": 1229300000},
-                    {"workgroups": 2280, "read_bytes": 2573200000, "write_bytes": 1227500000},
-                    {"workgroups": 3072, "read_bytes": 2570400000, "write_bytes": 1221500000},
-                    {"workgroups": 3248, "read_bytes": 2611400000, "write_bytes": 1219400000},
-                    {"workgroups": 4320, "read_bytes": 2709100000, "write_bytes": 1218900000},
-                    {"workgroups": 6488, "read_bytes": 2746400000, "write_bytes": 1197800000},
-                    {"workgroups": 8632, "read_bytes": 3024800000, "write_bytes": 1187800000},
-                    {"workgroups": 12944, "read_bytes": 3251800000, "write_bytes": 1187100000}],
-        "c5/fp32": [{"workgroups": 832, "read_bytes": 1203300000, "write_bytes": 587400000},
-                    {"workgroups": 1008, "read_bytes": 1304600000, "write_bytes": 621900000},
-                    {"workgroups": 1104, "read_bytes": 1281900000, "write_bytes": 614900000},
-                    {"workgroups": 1624, "read_bytes": 1290500000, "write_bytes": 614800000},
-                    {"workgroups": 2040, "read_bytes": 1304800000, "write_bytes": 616900000},
-                    {"workgroups": 2176, "read_bytes": 1305800000, "write_bytes": 616800000},
-                    {"workgroups": 3072, "read_bytes": 1320700000, "write_bytes": 607200000},
-                    {"workgroups": 3248, "read_bytes": 1321700000, "write_bytes": 604500000},
-                    {"workgroups": 4072, "read_bytes": 1348500000, "write_bytes": 595100000},
-                    {"workgroups": 4320, "read_bytes": 1360100000, "write_bytes": 598100000},
-                    {"workgroups": 6488, "read_bytes": 1434200000, "write_bytes": 582000000},
-                    {"workgroups": 8632, "read_bytes": 1495500000, "write_bytes": 579200000},
-                    {"workgroups": 12944, "read_bytes": 1591900000, "write_bytes": 577900000}],
+    "ff16fc62ca229356165fbb1057b71c8f77fc5caf20a03462583356d1cd0beb56": {
+        "c5/fp64": [{"workgroups": 760, "read_bytes": 2655800000, "write_bytes": 1235400000},
+                    {"workgroups": 832, "read_bytes": 2628700000, "write_bytes": 1233200000},
+                    {"workgroups": 1104, "read_bytes": 2596800000, "write_bytes": 1230900000},
+                    {"workgroups": 1520, "read_bytes": 2601400000, "write_bytes": 1235900000},
+                    {"workgroups": 1624, "read_bytes": 2590700000, "write_bytes": 1233100000},
+                    {"workgroups": 2176, "read_bytes": 2634600000, "write_bytes": 1232100000},
+                    {"workgroups": 2280, "read_bytes": 2617700000, "write_bytes": 1231400000},
+                    {"workgroups": 3072, "read_bytes": 2603300000, "write_bytes": 1226900000},
+                    {"workgroups": 3248, "read_bytes": 2642300000, "write_bytes": 1224700000},
+                    {"workgroups": 4320, "read_bytes": 2732500000, "write_bytes": 1221800000},
+                    {"workgroups": 6488, "read_bytes": 2761400000, "write_bytes": 1216600000},
+                    {"workgroups": 8632, "read_bytes": 3019600000, "write_bytes": 1198600000},
+                    {"workgroups": 12944, "read_bytes": 3226900000, "write_bytes": 1191600000}],
+        "c5/fp32": [{"workgroups": 832, "read_bytes": 1227400000, "write_bytes": 596400000},
+                    {"workgroups": 1008, "read_bytes": 1339600000, "write_bytes": 629000000},
+                    {"workgroups": 1104, "read_bytes": 1321500000, "write_bytes": 624800000},
+                    {"workgroups": 1624, "read_bytes": 1316100000, "write_bytes": 622300000},
+                    {"workgroups": 2040, "read_bytes": 1324700000, "write_bytes": 623600000},
+                    {"workgroups": 2176, "read_bytes": 1326100000, "write_bytes": 623400000},
+                    {"workgroups": 3072, "read_bytes": 1335600000, "write_bytes": 615600000},
+                    {"workgroups": 3248, "read_bytes": 1337800000, "write_bytes": 613300000},
+                    {"workgroups": 4072, "read_bytes": 1357100000, "write_bytes": 605900000},
+                    {"workgroups": 4320, "read_bytes": 1369000000, "write_bytes": 606200000},
+                    {"workgroups": 6488, "read_bytes": 1434000000, "write_bytes": 592300000},
+                    {"workgroups": 8632, "read_bytes": 1494800000, "write_bytes": 580000000},
+                    {"workgroups": 12944, "read_bytes": 1591700000, "write_bytes": 578000000}],
     },
 }
 
