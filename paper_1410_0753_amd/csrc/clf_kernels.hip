@@ -1274,7 +1274,8 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
           dma_row(cx.D, r, &lrow[slot][wave][1][0]);
           dma_row(cx.U, r, &lrow[slot][wave][2][0]);
           dma_row(cx.V, r, &lrow[slot][wave][3][0]);
-          if (do_max) {
+          // the maxwave pair of output rows only (march rows 2 HALO on)
+          if (do_max && i >= 2 * HALO) {
             dma_row(cx.emax, r - D * HALO, &lmw[slot][wave][0][0]);
             dma_row(cx.smax2, r - D * HALO, &lmw[slot][wave][1][0]);
           }
@@ -1305,20 +1306,28 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
             // step 2 HALO + kLdsAhead on, each of the kLdsAhead steps since
             // that issue has also stored its output row (h, u, v: one store
             // each, issued after the step's loads), so those stores may be
-            // in flight as well. (The conditional maxwave and gauge stores
+            // in flight as well, and every row since carries its maxwave
+            // pair. Before that, the count leaves out the stores and the
+            // maxwave pairs (march rows below 2 HALO load none), and at the
+            // end of the march it counts only the rows issued (none past the
+            // last): a count below the operations issued after row i still
+            // waits for row i. (The conditional maxwave and gauge stores
             // only add to the operations issued after row i.)
             constexpr int kRowOps = kVmRow + kVmMw, kRowOps0 = kVmRow;
             constexpr int kStores = kLdsAhead * 3;
-            if (i >= 2 * HALO + kLdsAhead) {
+            static_assert(kLdsAhead == 3, "the end-of-march waits below assume 3 rows ahead");
+            const int after = npush - 1 - i;
+            if (after <= 0) {
+              wait_vmem<0>();
+            } else if (after == 1) {
+              wait_vmem<kRowOps0>();
+            } else if (i >= 2 * HALO + kLdsAhead) {
               if (do_max)
                 wait_vmem<(kLdsAhead - 1) * kRowOps + kStores>();
               else
                 wait_vmem<(kLdsAhead - 1) * kRowOps0 + kStores>();
             } else {
-              if (do_max)
-                wait_vmem<(kLdsAhead - 1) * kRowOps>();
-              else
-                wait_vmem<(kLdsAhead - 1) * kRowOps0>();
+              wait_vmem<(kLdsAhead - 1) * kRowOps0>();
             }
             const int slot = i & (kLdsSlots - 1);
             // x view: w = u, t = v
@@ -1331,7 +1340,7 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
               m.e = 0;
               m.s2 = 0;
             }
-            issue_dir(i + kLdsAhead);
+            if (i + kLdsAhead < npush) issue_dir(i + kLdsAhead);
           } else {
             a = pf[K];
             m = pm[K];
@@ -1386,9 +1395,8 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
         }
         if (i < npush) body(std::integral_constant<int, 0>(), r_first + D * i, i);
         if (i + 1 < npush) body(std::integral_constant<int, 1>(), r_first + D * (i + 1), i + 1);
-        // the rows issued beyond the march must land before the LDS ring is
-        // reused (next tile) or released (end of the wavefront)
-        if (kLds) wait_vmem<0>();
+        // the loads of the last row have landed (its wait was for all
+        // operations), so the LDS ring is free for the next tile
       };
       if (rev)
         march(std::integral_constant<int, -1>());
