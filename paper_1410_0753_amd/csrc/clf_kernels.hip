@@ -1165,10 +1165,16 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
     };
     // maxwave values of an output row, read one march row ahead of use
     struct MW { R e, s2; };
+    // A row that is not one of the tile's output rows (the halo rows at the
+    // start of the march, the rows past its end) reads the maxwave of the
+    // first output row instead, which the tile reads anyway: the load is
+    // still issued (every path of the march issues the same loads, which
+    // keeps the compiler's waits as tight as before) but costs no new lines.
+    const int yout0 = tl.y0, yout1 = tl.y0 + tl.rows - 1;
     auto load_mw = [&](int r, MW& m) {
       m.e = 0; m.s2 = 0;
       if (do_max) {
-        const int rc = r < 0 ? 0 : (r >= ny ? ny - 1 : r);
+        const int rc = (r < yout0 || r > yout1) ? yout0 : r;
         const unsigned b = node(rc, xcl);
         m.e = ld(cx.emax, b);
         m.s2 = ld(cx.smax2, b);
@@ -1213,7 +1219,8 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
       for (int r = tl.y0; r < tl.y0 + tl.rows; ++r) {
         A a = nxt;
         MW m = mnxt;
-        load_row(r + 1, nxt);
+        // past the last row: the row in use again (its lines are loaded)
+        load_row(r < yout1 ? r + 1 : r, nxt);
         load_mw(r + 1, mnxt);
         R f = cload(xfac + r);
         C o = xsweep_row<P>(a, f * xiL, f * xiR, f * xiS, cx.par);
@@ -1344,7 +1351,9 @@ step_kernel(const GridDesc* __restrict__ grids, const Tile* __restrict__ tiles, 
           } else {
             a = pf[K];
             m = pm[K];
-            load_row(r + D * PF, pf[(K + PF) % 3]);
+            // past the end of the march: the last march row again (its
+            // lines are loaded by then; the slot is never read)
+            load_row(i + PF < npush ? r + D * PF : r_first + D * (npush - 1), pf[(K + PF) % 3]);
             load_mw(r + D * (1 - HALO), pm[(K + 1) % 3]);
           }
           const int ro = r - D * HALO;
