@@ -141,25 +141,70 @@ def test_full_size_2400x1800_fp64_long_bitwise(clf, oracle_mod):
     assert ever.sum() > 0
 
 
-def test_full_size_8000x6000_fp32_sampled(clf, oracle_mod):
-    # FP32 on the large grid: error against the FP64 oracle on sampled rows
+def test_full_size_8000x6000_fp32_whole_grid(clf, oracle_mod):
+    # FP32 on the large grid: error against the FP64 oracle on every node
+    # (eta relative to the amplitude, u and v relative to the largest speed),
+    # and the same wet set
     case = synth.config5(steps=4)
     print("full-size 8000x6000 FP32, 4 steps", flush=True)
     g = clf.Solver.from_case(case, precision=clf.FP32, autotune=1)
     g.set_initial(case.eta0)
     g.step(4)
-    eg, _, _, wg = (t.cpu().numpy() for t in g.state())
+    eg, ug, vg, wg = (t.cpu().numpy() for t in g.state())
     del g
     o = oracle_mod.Oracle.from_case(case)
     o.set_initial(case.eta0)
     o.step(4)
-    eo, _, _, wo = o.state()
-    rows = np.linspace(0, case.ny - 1, 64).astype(int)
+    eo, uo, vo, wo = o.state()
     amp = np.abs(eo).max()
-    err = np.abs(eg[rows] - eo[rows]).max() / amp
-    flips = (wg[rows] != wo[rows]).mean()
-    print("max eta err %.3e, flips %.3e" % (err, flips))
-    assert err <= 1e-4 and flips <= 1e-4
+    spd = max(np.abs(uo).max(), np.abs(vo).max())
+    err = np.abs(eg - eo).max() / amp
+    erru = max(np.abs(ug - uo).max(), np.abs(vg - vo).max()) / spd
+    print("max eta err %.3e, max u/v err %.3e" % (err, erru), flush=True)
+    assert np.array_equal(wg.astype(bool), wo.astype(bool))
+    assert err <= 1e-4 and erru <= 1e-4
+
+
+def test_full_size_8000x6000_fp32_against_fp64_200_steps(clf):
+    # 200 steps of the benchmark configuration (gauges, enclosed-grid series,
+    # maxwave every step) in FP32 against the FP64 path, which equals the
+    # oracle bit for bit in the parity tests: state, wet set and maxwave
+    case = synth.config5(steps=200)
+    out = {}
+    for prec in (clf.FP64, clf.FP32):
+        print("full-size 8000x6000", "fp32" if prec == clf.FP32 else "fp64", "200 steps", flush=True)
+        g = clf.Solver.from_case(
+            case, precision=prec, autotune=1, maxout=1, gout=10, gauge_capacity=40, bndout=1,
+            max_enclosed=len(case.enclosed),
+            max_enclosed_points=sum(2 * (len(x) + len(y)) for x, y in case.enclosed),
+            series_capacity=210)
+        g.set_gauges(case.gauges[:, 0], case.gauges[:, 1])
+        for ex, ey in case.enclosed:
+            g.add_enclosed_grid(ex, ey)
+        g.set_initial(case.eta0)
+        g.step(200)
+        out[prec] = ([t.cpu().numpy() for t in g.state()] + [t.cpu().numpy() for t in g.read_maxwave()]
+                     + [g.read_gauges()[0], g.read_boundary_series(0, 0)[0]])
+        del g
+    e64, u64, v64, w64, m64, s64, g64, b64 = out[clf.FP64]
+    e32, u32, v32, w32, m32, s32, g32, b32 = out[clf.FP32]
+    assert g64.shape == g32.shape and b64.shape == b32.shape
+    amp = np.abs(e64).max()
+    spd = max(np.abs(u64).max(), np.abs(v64).max())
+    err = np.abs(e32 - e64).max() / amp
+    erru = max(np.abs(u32 - u64).max(), np.abs(v32 - v64).max()) / spd
+    errm = np.abs(m32 - m64).max() / np.abs(m64).max()
+    errs = np.abs(s32 - s64).max() / np.abs(s64).max()
+    flips = (w32.astype(bool) != w64.astype(bool)).mean()
+    print("eta %.3e u/v %.3e eta_max %.3e speed_max %.3e flips %.3e" % (err, erru, errm, errs, flips),
+          flush=True)
+    assert err <= 1e-4 and erru <= 1e-4 and errm <= 1e-4 and errs <= 1e-4
+    assert flips <= 1e-6
+    # gauge and series records hold eta, u and v (at 200 steps the waves
+    # have not reached most of them): within the same bound of the wave's
+    # amplitude and largest speed
+    for r32, r64 in ((g32, g64), (b32, b64)):
+        assert np.abs(r32 - r64).max() <= 1e-4 * max(amp, spd)
 
 
 @pytest.mark.parametrize("seed", range(12))
