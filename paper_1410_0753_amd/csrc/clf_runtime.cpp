@@ -474,8 +474,10 @@ int autotune_segment(clf_ctx* c, int* best_seg) {
       return CLF_OK;
     }
   }
-  // fixed lengths plus the round-aligned ones for up to 4 workgroup waves
-  std::vector<int> cands = {16, 24, 32, 48, 64, 96, 128, 192, 256};
+  // fixed lengths (every 2 rows where the large grids have their optimum,
+  // which moves with the GPU by a few rows) plus the round-aligned ones for
+  // up to 4 workgroup waves
+  std::vector<int> cands = {16, 20, 24, 26, 28, 30, 32, 34, 36, 40, 48, 56, 64, 96, 128, 192, 256};
   for (int sg : grid_round_segments(c->nx, c->ny, c->slots, 4)) cands.push_back(sg);
   std::sort(cands.begin(), cands.end());
   cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
