@@ -67,32 +67,48 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1410_0753_amd", "csrc", "clf_kernels.hip"
 # (segment length), which the autotuner may choose differently run to run.
 TRAFFIC = {
     "8cecaa3c2c435b1331ff9755d0cb853e8f00bcb1395ee6870a17ebe8f8874d4e": {
-        "c5/fp64": [{"workgroups": 760, "read_bytes": 2628900000, "write_bytes": 1235400000},
-                    {"workgroups": 832, "read_bytes": 2601700000, "write_bytes": 1233000000},
-                    {"workgroups": 1104, "read_bytes": 2552500000, "write_bytes": 1230300000},
-                    {"workgroups": 1520, "read_bytes": 2569400000, "write_bytes": 1235300000},
-                    {"workgroups": 1624, "read_bytes": 2556700000, "write_bytes": 1233200000},
-                    {"workgroups": 2176, "read_bytes": 2545800000, "write_bytes": 1231500000},
-                    {"workgroups": 2280, "read_bytes": 2545900000, "write_bytes": 1231000000},
-                    {"workgroups": 3072, "read_bytes": 2538200000, "write_bytes": 1225700000},
-                    {"workgroups": 3248, "read_bytes": 2542200000, "write_bytes": 1223700000},
-                    {"workgroups": 4320, "read_bytes": 2570400000, "write_bytes": 1219900000},
-                    {"workgroups": 6488, "read_bytes": 2640000000, "write_bytes": 1208200000},
-                    {"workgroups": 8632, "read_bytes": 2747000000, "write_bytes": 1206600000},
-                    {"workgroups": 12944, "read_bytes": 2940100000, "write_bytes": 1190100000}],
-        "c5/fp32": [{"workgroups": 832, "read_bytes": 1190200000, "write_bytes": 588900000},
-                    {"workgroups": 1008, "read_bytes": 1304100000, "write_bytes": 627100000},
-                    {"workgroups": 1104, "read_bytes": 1278900000, "write_bytes": 620900000},
-                    {"workgroups": 1624, "read_bytes": 1256900000, "write_bytes": 617600000},
-                    {"workgroups": 2040, "read_bytes": 1260500000, "write_bytes": 619600000},
-                    {"workgroups": 2176, "read_bytes": 1259400000, "write_bytes": 619600000},
-                    {"workgroups": 3072, "read_bytes": 1245500000, "write_bytes": 609000000},
-                    {"workgroups": 3248, "read_bytes": 1245000000, "write_bytes": 606400000},
-                    {"workgroups": 4072, "read_bytes": 1250400000, "write_bytes": 600200000},
-                    {"workgroups": 4320, "read_bytes": 1255900000, "write_bytes": 596700000},
-                    {"workgroups": 6488, "read_bytes": 1294200000, "write_bytes": 581900000},
-                    {"workgroups": 8632, "read_bytes": 1324700000, "write_bytes": 578300000},
-                    {"workgroups": 12944, "read_bytes": 1354000000, "write_bytes": 577200000}],
+        "c5/fp64": [{"workgroups": 760, "read_bytes": 2625000000, "write_bytes": 1233900000},
+                    {"workgroups": 832, "read_bytes": 2601900000, "write_bytes": 1232700000},
+                    {"workgroups": 1104, "read_bytes": 2550600000, "write_bytes": 1230700000},
+                    {"workgroups": 1520, "read_bytes": 2564900000, "write_bytes": 1236500000},
+                    {"workgroups": 1624, "read_bytes": 2553200000, "write_bytes": 1234900000},
+                    {"workgroups": 2176, "read_bytes": 2543100000, "write_bytes": 1234400000},
+                    {"workgroups": 2280, "read_bytes": 2545900000, "write_bytes": 1234500000},
+                    {"workgroups": 3072, "read_bytes": 2536900000, "write_bytes": 1230100000},
+                    {"workgroups": 3248, "read_bytes": 2541100000, "write_bytes": 1228200000},
+                    {"workgroups": 3728, "read_bytes": 2549900000, "write_bytes": 1227700000},
+                    {"workgroups": 4320, "read_bytes": 2569500000, "write_bytes": 1224300000},
+                    {"workgroups": 5176, "read_bytes": 2596300000, "write_bytes": 1218100000},
+                    {"workgroups": 5768, "read_bytes": 2621400000, "write_bytes": 1216500000},
+                    {"workgroups": 6112, "read_bytes": 2632800000, "write_bytes": 1212200000},
+                    {"workgroups": 6488, "read_bytes": 2638700000, "write_bytes": 1210600000},
+                    {"workgroups": 6904, "read_bytes": 2667700000, "write_bytes": 1207100000},
+                    {"workgroups": 7424, "read_bytes": 2692400000, "write_bytes": 1211000000},
+                    {"workgroups": 7976, "read_bytes": 2703700000, "write_bytes": 1202300000},
+                    {"workgroups": 8632, "read_bytes": 2746500000, "write_bytes": 1199400000},
+                    {"workgroups": 10352, "read_bytes": 2813000000, "write_bytes": 1189800000},
+                    {"workgroups": 12944, "read_bytes": 2939700000, "write_bytes": 1191200000}],
+        "c5/fp32": [{"workgroups": 832, "read_bytes": 1190200000, "write_bytes": 589200000},
+                    {"workgroups": 1008, "read_bytes": 1303900000, "write_bytes": 627400000},
+                    {"workgroups": 1104, "read_bytes": 1283700000, "write_bytes": 621700000},
+                    {"workgroups": 1624, "read_bytes": 1261300000, "write_bytes": 618100000},
+                    {"workgroups": 2040, "read_bytes": 1261400000, "write_bytes": 620100000},
+                    {"workgroups": 2176, "read_bytes": 1260100000, "write_bytes": 620200000},
+                    {"workgroups": 3072, "read_bytes": 1246300000, "write_bytes": 609300000},
+                    {"workgroups": 3248, "read_bytes": 1244700000, "write_bytes": 606400000},
+                    {"workgroups": 3728, "read_bytes": 1249800000, "write_bytes": 602900000},
+                    {"workgroups": 4072, "read_bytes": 1250700000, "write_bytes": 597200000},
+                    {"workgroups": 4320, "read_bytes": 1256300000, "write_bytes": 597000000},
+                    {"workgroups": 5176, "read_bytes": 1269800000, "write_bytes": 588200000},
+                    {"workgroups": 5768, "read_bytes": 1281000000, "write_bytes": 584700000},
+                    {"workgroups": 6112, "read_bytes": 1288000000, "write_bytes": 583600000},
+                    {"workgroups": 6488, "read_bytes": 1293700000, "write_bytes": 582500000},
+                    {"workgroups": 6904, "read_bytes": 1301100000, "write_bytes": 584300000},
+                    {"workgroups": 7424, "read_bytes": 1309900000, "write_bytes": 580200000},
+                    {"workgroups": 7976, "read_bytes": 1316100000, "write_bytes": 578900000},
+                    {"workgroups": 8632, "read_bytes": 1324300000, "write_bytes": 578600000},
+                    {"workgroups": 10352, "read_bytes": 1335400000, "write_bytes": 577600000},
+                    {"workgroups": 12944, "read_bytes": 1353900000, "write_bytes": 577200000}],
     },
 }
 
