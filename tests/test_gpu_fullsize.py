@@ -1,8 +1,6 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
 times (autotuned segment, gauges, maxwave every step), plus randomised tiny
 grids (edge cases: 3-node lines, ragged strips and segments)."""
-import os
-
 import numpy as np
 import pytest
 
@@ -111,8 +109,6 @@ def test_reduced_8000x6000_runup_floods_plane_beaches(clf, oracle_mod):
     assert flooded.sum() >= 50
 
 
-@pytest.mark.skipif(os.environ.get("CLF_LONG_TESTS") != "1",
-                    reason="long run (about a minute of oracle time); set CLF_LONG_TESTS=1")
 def test_full_size_2400x1800_fp64_long_bitwise(clf, oracle_mod):
     # 2000 steps: the waves reach the coast after about 1000, and a few
     # hundred initially dry nodes flood and dry again; state, gauges and
