@@ -1799,7 +1799,7 @@ int ens_default_segment(const clf_ens* e) {
 }
 
 int ens_autotune(clf_ens* e, int* best) {
-  std::vector<int> cands = {16, 24, 32, 48, 64, 96, 128};
+  std::vector<int> cands = {16, 20, 24, 26, 28, 30, 32, 34, 36, 40, 48, 64, 96, 128};
   for (int sg : ens_round_segments(e, 4)) cands.push_back(sg);
   std::sort(cands.begin(), cands.end());
   cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
